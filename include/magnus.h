@@ -1,0 +1,251 @@
+/*
+ * magnus.h -- C ABI of the MI355X Magnus-Leja propagator.
+ *
+ * Problem (Section 1, the Schroedinger equation; Section 4, the split of the
+ * Hamiltonian):  i dpsi/dt = H(t) psi,  H(t) = H1 + f(t) H2,  H1, H2 Hermitian,
+ * psi(t0) = psi0.  With A(t) = -i H(t) (Section 2 writes Y' = A(t) Y), one step
+ * of size tau is Y_{n+1} = exp(Omega_n) Y_n (Section 2, the one-step scheme),
+ * and every exponential is applied to the state by Newton interpolation at
+ * Leja points (Section 3).  Each exponent handled here has the form
+ *
+ *     Omega = -i tau H_hat,   H_hat = a H1 + b H2 + kappa K,   K = i [H1, H2],
+ *
+ * so exp(Omega) v = exp(-i tau H_hat) v with a Hermitian H_hat.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are complex128, interleaved (re, im) pairs of IEEE
+ *   doubles, the layout of torch.complex128 / numpy complex128 / hipDoubleComplex.
+ * - A state of dimension dim is dim contiguous complex128 values; a batch of
+ *   `batch` states is batch*dim values, state b starting at element b*dim.
+ * - All vector and matrix pointers are DEVICE pointers on the context's device,
+ *   allocated and freed by the caller; the library never frees them, keeps no
+ *   reference to them after a call returns, and never writes to inputs.
+ * - Scalars, option structs, f-node arrays and stats are HOST memory.
+ * - Calls enqueue work on `stream` (a hipStream_t; NULL = the default stream)
+ *   and return without synchronising, unless a non-NULL `stats` is passed, in
+ *   which case the call synchronises `stream` before returning.  A context
+ *   owns one workspace: calls that share a context must be ordered on one
+ *   stream (calls on different streams through one context race).
+ * - Return value: MAGNUS_OK (0) or a negative status; magnus_last_error()
+ *   returns a thread-local message describing the last failure.
+ * - Precision: all arithmetic is FP64 (device and host).
+ */
+#ifndef MAGNUS_H
+#define MAGNUS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MAGNUS_OK        0
+#define MAGNUS_EINVAL   -1  /* null pointer, size mismatch, bad format, malformed CSR */
+#define MAGNUS_EDOMAIN  -2  /* tol <= 0, non-finite tau/f/a/b/kappa, lam_min > lam_max */
+#define MAGNUS_ENOCONV  -3  /* the degree/substep caps cannot meet tol (nothing enqueued) */
+#define MAGNUS_EHIP     -4  /* HIP runtime error */
+#define MAGNUS_ENOMEM   -5  /* dim or batch larger than the context workspace */
+#define MAGNUS_ENAN     -6  /* non-finite value met on the device (magnus_check) */
+
+/* ---- term formats -------------------------------------------------------- */
+#define MAGNUS_CSR    0
+#define MAGNUS_DENSE  1
+
+/* ---- methods ---------------------------------------------------------------- */
+#define MAGNUS_CF4  0   /* Section 2, Method Cf4 */
+#define MAGNUS_M4   1   /* Section 2, Method M4  */
+
+/* Largest interpolation degree per substep the library plans for. */
+#define MAGNUS_MAX_DEGREE 64
+
+typedef struct magnus_ctx magnus_ctx;
+typedef void* magnus_stream;   /* hipStream_t */
+
+/*
+ * One Hermitian term of the Hamiltonian.
+ *   format  MAGNUS_CSR: row_ptr[dim+1] (row_ptr[0] = 0, non-decreasing,
+ *           row_ptr[dim] = nnz), col_idx[nnz] (0 <= col < dim), val[nnz]
+ *           complex128.  Section 3 fixes CSR as the sparse format.
+ *           MAGNUS_DENSE: val is a row-major dim x dim complex128 matrix with
+ *           row stride ld >= dim elements (element (i, j) at val[i*ld + j]);
+ *           row_ptr, col_idx, nnz unused.
+ *   lam_min, lam_max  an enclosure of the term's spectrum (Section 3: the Leja
+ *           method needs an estimate of the spectrum).  Fill them with
+ *           magnus_spectral_bounds or supply them; lam_min <= lam_max.
+ */
+typedef struct {
+  int32_t format;
+  int32_t reserved;
+  int64_t dim;
+  int64_t nnz;
+  int64_t ld;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const void* val;
+  double lam_min;
+  double lam_max;
+} magnus_term;
+
+/* H(t) = H1 + f(t) H2 (Section 4).  k_min, k_max enclose the spectrum of the
+ * Hermitian K = i [H1, H2] (needed by M4 only; magnus_spectral_bounds fills
+ * them with the rigorous bound |K| <= 2 |H1| |H2|). */
+typedef struct {
+  magnus_term H1;
+  magnus_term H2;
+  double k_min;
+  double k_max;
+} magnus_hamiltonian;
+
+/* Leja options (Section 4 runs with relative and absolute tolerance 1e-10 and
+ * early termination on).
+ *   tol               error allowed per exponential, relative to |v|_2
+ *                     (tol_mode 0), or for the whole call, split evenly over
+ *                     its exponentials (tol_mode 1).
+ *   max_degree        cap on the degree per substep (1..MAGNUS_MAX_DEGREE).
+ *   max_substeps      cap on the number of substeps per exponential (>= 1).
+ *   early_termination 1: stop a substep once two consecutive Newton terms
+ *                     are below tol |v| (Section 3); 0: always run the a
+ *                     priori degree (a result that is smooth in the data). */
+typedef struct {
+  double tol;
+  int32_t max_degree;
+  int32_t max_substeps;
+  int32_t early_termination;
+  int32_t tol_mode;
+} magnus_leja_opts;
+
+/* Work done by one call (filled when non-NULL; implies a stream sync). */
+typedef struct {
+  int64_t exponentials;     /* exponentials applied (per state) */
+  int64_t substeps;         /* substeps over all exponentials */
+  int64_t planned_iters;    /* Leja iterations planned a priori */
+  int64_t iters;            /* Leja iterations executed (early termination) */
+  int64_t hv_products;      /* products of a CSR/dense term with a vector */
+  int32_t max_degree_used;
+  int32_t max_substeps_used;
+  double max_err_bound;     /* largest a priori interpolation bound per exponential */
+  double tol_per_exp;       /* tolerance each exponential was planned for */
+} magnus_stats;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Create a context on `device` owning a workspace for states of up to
+ * max_dim entries and batches of up to max_batch states (the only device
+ * allocation the library makes; about 8 vectors per state).  *out receives the
+ * context.  Errors: EINVAL (null out, max_dim < 1, max_batch < 1),
+ * EHIP (device or allocation failure). */
+int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t device);
+
+/* Free the workspace and the context (NULL is accepted). */
+int magnus_destroy(magnus_ctx* ctx);
+
+/* Thread-local description of the last non-OK status. */
+const char* magnus_last_error(void);
+
+/* Synchronise `stream` and report device-side failures since the last check:
+ * MAGNUS_ENAN if a non-finite vector norm was met, else MAGNUS_OK. */
+int magnus_check(magnus_ctx* ctx, magnus_stream stream);
+
+/* ---- spectral bounds (Section 3: the parameters of the Leja method need an
+ * estimate of the spectrum) --------------------------------------------------- */
+
+/* Fill h->H1.lam_min/lam_max, h->H2.lam_min/lam_max (Gershgorin discs, rigorous
+ * for Hermitian terms) and h->k_min/k_max (|K| <= 2 |H1| |H2|).  Also validates
+ * CSR structure (row_ptr monotone, row_ptr[0] = 0, row_ptr[dim] = nnz, columns
+ * in range) and returns EINVAL if it is malformed.  Synchronous. */
+int magnus_spectral_bounds(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
+
+/* ---- the hot path ------------------------------------------------------------ */
+
+/* w = exp(-i tau (a H1 + b H2 + kappa K)) v for `batch` states
+ * (Section 3: the Leja interpolant sum_i d_i prod_{j<i} (A - xi_j I) v and its
+ * recurrence).  v and w hold batch*dim complex128; w may equal v.
+ * tau may be negative or zero (zero copies v).  kappa != 0 applies
+ * K w = i (H1 (H2 w) - H2 (H1 w)) matrix-free.
+ * Errors: EINVAL, EDOMAIN, ENOMEM, ENOCONV (before any work is enqueued), EHIP. */
+int expmv_leja(magnus_ctx* ctx, const magnus_hamiltonian* h, double a, double b, double kappa,
+               double tau, const void* v, void* w, int32_t batch, const magnus_leja_opts* opts,
+               magnus_stats* stats, magnus_stream stream);
+
+/* One step of Method Cf4 (Section 2):
+ *   psi_out = exp(tau(alpha1 A1 + alpha2 A2)) exp(tau(alpha2 A1 + alpha1 A2)) psi_in,
+ * the right factor acting first, with A_j = -i (H1 + f_j H2), f1 = f(t_n + c1 tau),
+ * f2 = f(t_n + c2 tau), c_{1,2} = 1/2 -+ sqrt(3)/6, alpha_{1,2} = (3 -+ 2 sqrt(3))/12.
+ * The caller evaluates f at the nodes (magnus_quadrature_nodes gives them).
+ * psi_in may equal psi_out.  Errors as expmv_leja. */
+int magnus_step_cf4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1, double f2,
+                    const void* psi_in, void* psi_out, int32_t batch, const magnus_leja_opts* opts,
+                    magnus_stats* stats, magnus_stream stream);
+
+/* One step of Method M4 (Section 2):
+ *   psi_out = exp(tau/2 (A1 + A2) + sqrt(3) tau^2 / 12 [A2, A1]) psi_in,
+ * i.e. exp(-i tau (H1 + fbar H2 + kappa K)) with fbar = (f1 + f2)/2,
+ * kappa = sqrt(3) tau (f2 - f1) / 12, K = i [H1, H2]; the commutator is
+ * applied to vectors, never assembled.  Arguments as magnus_step_cf4. */
+int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1, double f2,
+                   const void* psi_in, void* psi_out, int32_t batch, const magnus_leja_opts* opts,
+                   magnus_stats* stats, magnus_stream stream);
+
+/* nsteps steps of `method` (MAGNUS_CF4 or MAGNUS_M4) in place on psi
+ * (batch*dim complex128, device) on the grid t_n = t0 + n tau (the one-step
+ * scheme of Section 2 repeated; control flow stays on the host, Section 3).
+ *   f_nodes     HOST double[batch_f][nsteps][2]: f(t_n + c1 tau), f(t_n + c2 tau).
+ *   batch_f     1 (one field for all states) or batch (one field per state).
+ *   checkpoints NULL, or DEVICE storage for ceil(nsteps/every_k)+1 copies of psi:
+ *               slot j receives psi after j*every_k steps (slot 0 = psi0), and
+ *               the last slot psi after nsteps steps.
+ *   every_k     checkpoint spacing (>= 1; ignored when checkpoints is NULL).
+ * Errors as expmv_leja. */
+int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, double tau,
+              int64_t nsteps, const double* f_nodes, int32_t batch_f, void* psi, int32_t batch,
+              void* checkpoints, int32_t every_k, const magnus_leja_opts* opts,
+              magnus_stats* stats, magnus_stream stream);
+
+/* ---- kernel timing (profiling aid) ---------------------------------------------- */
+
+/* Kernel classes timed by magnus_timing. */
+#define MAGNUS_KERNEL_CSR_LEJA   0  /* two-term CSR Leja iteration */
+#define MAGNUS_KERNEL_CSR_SPLIT  1  /* first pass of a commutator iteration */
+#define MAGNUS_KERNEL_CSR_COMM   2  /* second pass of a commutator iteration */
+#define MAGNUS_KERNEL_DENSE_LEJA 3  /* two-term dense Leja iteration */
+
+/* enable = 1: from now on bracket every iteration kernel the context launches
+ * with a pair of HIP events on the call's stream (previous records are
+ * dropped); enable = 0: stop recording.  Errors: EINVAL, EHIP. */
+int magnus_timing(magnus_ctx* ctx, int32_t enable);
+
+/* Wait for the recorded events and report, for one kernel class, the summed
+ * event-to-event time in milliseconds and the number of launches.
+ * Errors: EINVAL (bad class), EHIP. */
+int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
+
+/* ---- host planning helpers (pure host code, no device needed) ------------------- */
+
+/* t_out[2n + j] = t0 + n tau + c_{j+1} tau for n < nsteps, j in {0, 1}: the two
+ * Gauss nodes shared by Methods M4 and Cf4 (Section 2). */
+int magnus_quadrature_nodes(int32_t method, double t0, double tau, int64_t nsteps, double* t_out);
+
+/* The first m+1 Leja points of [-2, 2]: xi_0 = 2, then each point maximises
+ * the product of distances to the previous ones (ties to the left). */
+int magnus_leja_points(int32_t m, double* xi);
+
+/* Divided differences d_k = f[xi_0, ..., xi_k], k = 0..m, of f(x) = exp(-i theta x)
+ * at the Leja points (Section 3), written as m+1 interleaved complex values. */
+int magnus_divided_differences(double theta, int32_t m, double* d);
+
+/* sup over x in [-2, 2] of |exp(-i theta x) - p_m(x)| (p_m the degree-m Leja
+ * interpolant), evaluated on the planner's grid from the tail of the Newton series. */
+double magnus_leja_error(double theta, int32_t m);
+
+/* Degree m and substeps s chosen for exp(-i theta X), spec(X) in [-2, 2], so
+ * that s * err(theta/s, m) <= tol / 2 at least cost m*s; *bound receives the
+ * achieved s * err.  Returns ENOCONV if the caps cannot meet tol. */
+int magnus_leja_plan(double theta, double tol, int32_t max_degree, int32_t max_substeps,
+                     int32_t* m, int32_t* s, double* bound);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAGNUS_H */

@@ -1,0 +1,654 @@
+// The C ABI of libmagnus (declared in include/magnus.h).
+//
+// Host side of the hot path: argument validation, per-exponential Leja
+// planning (planner.h), buffer rotation for the Newton recurrence and its
+// substeps, and the two fourth-order Magnus steps of Section 2 (Cf4, M4)
+// built from chained exponentials.  All device work is in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/magnus.h"
+#include "kernels.h"
+#include "planner.h"
+
+using magnus::CsrDev;
+using magnus::ExpPlan;
+using magnus::IterArgs;
+using magnus::Slot;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(MAGNUS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Workspace vectors per state.
+enum Vec { kA = 0, kB, kS0, kS1, kS2, kU, kV, kNumVec };
+
+}  // namespace
+
+struct magnus_ctx {
+  int device = 0;
+  int64_t max_dim = 0;
+  int32_t max_batch = 0;
+  double2* vecs = nullptr;     // kNumVec * max_dim (states are processed in turn)
+  Slot* slots = nullptr;       // one control block
+  double* partials = nullptr;  // 2 * max_grid
+  int64_t max_grid = 0;
+  double* scan = nullptr;      // per-workgroup outputs of the Gershgorin scans
+  int64_t scan_len = 0;
+  std::set<std::tuple<const void*, const void*, const void*, int64_t, int64_t>> validated;
+  std::mutex mu;
+  // kernel timing: (kind, start, stop) per recorded launch, events reused from a pool
+  bool timing = false;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+
+  double2* vec(int k) { return vecs + (size_t)k * (size_t)max_dim; }
+};
+
+namespace {
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+int check_term(const magnus_term& t, int64_t dim, const char* name) {
+  if (t.format != MAGNUS_CSR && t.format != MAGNUS_DENSE)
+    return fail(MAGNUS_EINVAL, "%s: unknown format %d", name, t.format);
+  if (t.dim != dim) return fail(MAGNUS_EINVAL, "%s: dim %lld != %lld", name, (long long)t.dim, (long long)dim);
+  if (!t.val) return fail(MAGNUS_EINVAL, "%s: null val", name);
+  if (t.format == MAGNUS_CSR) {
+    if (!t.row_ptr || !t.col_idx) return fail(MAGNUS_EINVAL, "%s: null CSR index array", name);
+    if (t.nnz < 0 || t.nnz > INT32_MAX) return fail(MAGNUS_EINVAL, "%s: nnz %lld out of range", name, (long long)t.nnz);
+  } else {
+    if (t.ld < dim) return fail(MAGNUS_EINVAL, "%s: ld %lld < dim", name, (long long)t.ld);
+  }
+  if (!is_fin(t.lam_min) || !is_fin(t.lam_max) || t.lam_min > t.lam_max)
+    return fail(MAGNUS_EDOMAIN, "%s: spectral enclosure [%g, %g] invalid", name, t.lam_min, t.lam_max);
+  return MAGNUS_OK;
+}
+
+int check_ham(magnus_ctx* ctx, const magnus_hamiltonian* h, int need_k) {
+  if (!ctx) return fail(MAGNUS_EINVAL, "null context");
+  if (!h) return fail(MAGNUS_EINVAL, "null hamiltonian");
+  const int64_t dim = h->H1.dim;
+  if (dim < 1) return fail(MAGNUS_EINVAL, "dim %lld < 1", (long long)dim);
+  if (dim > ctx->max_dim) return fail(MAGNUS_ENOMEM, "dim %lld exceeds workspace max_dim %lld", (long long)dim, (long long)ctx->max_dim);
+  if (dim > INT32_MAX / 2) return fail(MAGNUS_EINVAL, "dim %lld too large", (long long)dim);
+  int rc = check_term(h->H1, dim, "H1");
+  if (rc) return rc;
+  rc = check_term(h->H2, dim, "H2");
+  if (rc) return rc;
+  if (h->H1.format != h->H2.format) return fail(MAGNUS_EINVAL, "H1 and H2 must share a format");
+  if (need_k && (!is_fin(h->k_min) || !is_fin(h->k_max) || h->k_min > h->k_max))
+    return fail(MAGNUS_EDOMAIN, "commutator enclosure [%g, %g] invalid", h->k_min, h->k_max);
+  return MAGNUS_OK;
+}
+
+int check_opts(const magnus_leja_opts* o) {
+  if (!o) return fail(MAGNUS_EINVAL, "null options");
+  if (!(o->tol > 0.0) || !is_fin(o->tol)) return fail(MAGNUS_EDOMAIN, "tol %g must be positive and finite", o->tol);
+  if (o->max_degree < 1 || o->max_degree > MAGNUS_MAX_DEGREE)
+    return fail(MAGNUS_EINVAL, "max_degree %d outside 1..%d", o->max_degree, MAGNUS_MAX_DEGREE);
+  if (o->max_substeps < 1) return fail(MAGNUS_EINVAL, "max_substeps %d < 1", o->max_substeps);
+  if (o->tol_mode != 0 && o->tol_mode != 1) return fail(MAGNUS_EINVAL, "tol_mode %d", o->tol_mode);
+  return MAGNUS_OK;
+}
+
+// Structural check (and Gershgorin enclosure) of a CSR term, run once per term.
+int csr_scan(magnus_ctx* ctx, const magnus_term& t, hipStream_t s, double* lo, double* hi) {
+  const int dim = (int)t.dim;
+  const int grid = magnus::csr_gershgorin_grid(dim);
+  if (3 * (int64_t)grid > ctx->scan_len) return fail(MAGNUS_ENOMEM, "scan buffer too small");
+  double* dout = ctx->scan;
+  CsrDev d{t.row_ptr, t.col_idx, reinterpret_cast<const double2*>(t.val)};
+  hipError_t e = magnus::launch_csr_gershgorin(d, dim, t.nnz, dout, grid, s);
+  std::vector<double> h(3 * (size_t)grid);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dout, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(MAGNUS_EHIP, "CSR scan: %s", hipGetErrorString(e));
+  double a = INFINITY, b = -INFINITY;
+  bool bad = false;
+  for (int g = 0; g < grid; ++g) {
+    a = std::fmin(a, h[3 * g]);
+    b = std::fmax(b, h[3 * g + 1]);
+    bad = bad || h[3 * g + 2] != 0.0;
+  }
+  if (bad) return fail(MAGNUS_EINVAL, "malformed CSR (row_ptr not monotone / not 0..nnz, or column out of range)");
+  *lo = a;
+  *hi = b;
+  auto key = std::make_tuple((const void*)t.row_ptr, (const void*)t.col_idx, t.val, t.dim, t.nnz);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->validated.insert(key);
+  return MAGNUS_OK;
+}
+
+int ensure_valid(magnus_ctx* ctx, const magnus_hamiltonian* h, hipStream_t s) {
+  for (const magnus_term* t : {&h->H1, &h->H2}) {
+    if (t->format != MAGNUS_CSR) continue;
+    auto key = std::make_tuple((const void*)t->row_ptr, (const void*)t->col_idx, t->val, t->dim, t->nnz);
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      if (ctx->validated.count(key)) continue;
+    }
+    double lo, hi;
+    int rc = csr_scan(ctx, *t, s, &lo, &hi);
+    if (rc) return rc;
+  }
+  return MAGNUS_OK;
+}
+
+int dense_scan(magnus_ctx* ctx, const magnus_term& t, hipStream_t s, double* lo, double* hi) {
+  const int dim = (int)t.dim;
+  const int grid = magnus::dense_gershgorin_grid(dim);
+  if (2 * (int64_t)grid > ctx->scan_len) return fail(MAGNUS_ENOMEM, "scan buffer too small");
+  double* dout = ctx->scan;
+  hipError_t e = magnus::launch_dense_gershgorin(reinterpret_cast<const double2*>(t.val), dim, t.ld, dout, grid, s);
+  std::vector<double> h(2 * (size_t)grid);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dout, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(MAGNUS_EHIP, "dense scan: %s", hipGetErrorString(e));
+  double a = INFINITY, b = -INFINITY;
+  for (int g = 0; g < grid; ++g) { a = std::fmin(a, h[2 * g]); b = std::fmax(b, h[2 * g + 1]); }
+  *lo = a;
+  *hi = b;
+  return MAGNUS_OK;
+}
+
+// Host-side record of the work a call enqueued.
+struct Acc {
+  int64_t exponentials = 0, substeps = 0, planned = 0;
+  int32_t max_m = 0, max_s = 0;
+  double max_bound = 0.0;
+  int products_per_iter = 2;
+};
+
+struct ExpOp {
+  const magnus_hamiltonian* h;
+  double a, b, kappa;
+};
+
+int rows_per_block(int64_t dim) { return dim >= 65536 ? 64 : 16; }
+
+hipEvent_t next_event(magnus_ctx* ctx) {
+  if (ctx->pool_used == ctx->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->pool.push_back(e);
+  }
+  return ctx->pool[ctx->pool_used++];
+}
+
+// Launch f() on stream s, bracketed by events when the context records timings.
+template <class F>
+hipError_t timed(magnus_ctx* ctx, int kind, hipStream_t s, F f) {
+  if (!ctx->timing) return f();
+  hipEvent_t a = next_event(ctx), b = next_event(ctx);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = f();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) ctx->records.emplace_back(kind, a, b);
+  return e;
+}
+
+// Launch one Leja iteration (both passes for a commutator exponent).
+int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, const double2* win,
+                     double2* wout, double2* pacc, double tol_sub, int early, hipStream_t s) {
+  const magnus_hamiltonian* h = op.h;
+  const int dim = (int)h->H1.dim;
+  const auto& xi = magnus::leja_points();
+  IterArgs a{};
+  a.slot = ctx->slots;
+  a.partials = ctx->partials;
+  a.a1 = P.scale * op.a;
+  a.a2 = P.scale * op.b;
+  a.kap = P.scale * op.kappa;
+  a.sigma = P.scale * P.c + xi[i - 1];
+  a.d = make_double2(P.d[i].real(), P.d[i].imag());
+  a.d0 = make_double2(P.d[0].real(), P.d[0].imag());
+  a.dabs = std::abs(P.d[i]);
+  a.d0abs = std::abs(P.d[0]);
+  a.tol = tol_sub;
+  a.early = early;
+  a.first = (i == 1);
+  a.check_stop = (i != 1);
+  a.wcur = win;
+  a.wout = wout;
+  a.pacc = pacc;
+  if (h->H1.format == MAGNUS_DENSE) {
+    if (op.kappa != 0.0) return fail(MAGNUS_EINVAL, "commutator exponents need CSR terms");
+    a.x1 = win;
+    a.x2 = win;
+    HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_LEJA, s, [&] {
+      return magnus::launch_dense2_iter(reinterpret_cast<const double2*>(h->H1.val),
+                                        reinterpret_cast<const double2*>(h->H2.val), dim, h->H1.ld, a, s);
+    }));
+    return MAGNUS_OK;
+  }
+  CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
+  CsrDev t2{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
+  const int rpb = rows_per_block(dim);
+  if (op.kappa == 0.0) {
+    a.x1 = win;
+    a.x2 = win;
+    HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA, s,
+                  [&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }));
+    return MAGNUS_OK;
+  }
+  // commutator: pass 1 writes U = H1 w, V = H2 w; pass 2 applies H1 V and H2 U
+  double2* U = ctx->vec(kU);
+  double2* V = ctx->vec(kV);
+  IterArgs p1 = a;
+  p1.x1 = win;
+  p1.x2 = win;
+  p1.wout = U;
+  p1.pacc = V;
+  HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_SPLIT, s,
+                [&] { return magnus::launch_csr2_iter(magnus::kSplit, t1, t2, dim, p1, rpb, s); }));
+  a.x1 = V;
+  a.x2 = U;
+  HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_COMM, s,
+                [&] { return magnus::launch_csr2_iter(magnus::kLejaComm, t1, t2, dim, a, rpb, s); }));
+  return MAGNUS_OK;
+}
+
+// dst = exp(-i tau (a H1 + b H2 + kappa K)) src for one state.  dst may equal
+// src and may be kS2; it must not be another workspace vector.
+int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2* src, double2* dst,
+                    double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  const int64_t dim = op.h->H1.dim;
+  if (tau == 0.0) {
+    if (src != dst) HIP_TRY(magnus::launch_copy(src, dst, dim, s));
+    acc->exponentials += 1;
+    return MAGNUS_OK;
+  }
+  double lo, hi;
+  magnus::weyl_interval(op.a, op.h->H1.lam_min, op.h->H1.lam_max, op.b, op.h->H2.lam_min, op.h->H2.lam_max,
+                        op.kappa, op.h->k_min, op.h->k_max, &lo, &hi);
+  ExpPlan P;
+  if (!magnus::plan_exponential(tau, lo, hi, tol_e, o->max_degree, o->max_substeps, &P))
+    return fail(MAGNUS_ENOCONV, "no degree <= %d with <= %d substeps reaches tol %g (theta %g)",
+                o->max_degree, o->max_substeps, tol_e, 0.5 * std::fabs(tau) * 0.5 * (hi - lo));
+  const int m = P.lp.m, ns = P.lp.s;
+  const double tol_sub = tol_e / (2.0 * ns);
+  const double2* cur = src;
+  for (int sub = 0; sub < ns; ++sub) {
+    const bool last = (sub == ns - 1);
+    double2* Pbuf;
+    if (last && dst != cur) Pbuf = dst;
+    else Pbuf = (cur == ctx->vec(kS0)) ? ctx->vec(kS1) : ctx->vec(kS0);
+    for (int i = 1; i <= m; ++i) {
+      const double2* win = (i == 1) ? cur : ((i - 1) % 2 == 1 ? ctx->vec(kA) : ctx->vec(kB));
+      double2* wout = (i % 2 == 1) ? ctx->vec(kA) : ctx->vec(kB);
+      int rc = launch_iteration(ctx, op, P, i, win, wout, Pbuf, tol_sub, o->early_termination, s);
+      if (rc) return rc;
+    }
+    cur = Pbuf;
+  }
+  if (cur != dst) HIP_TRY(magnus::launch_copy(cur, dst, dim, s));
+  acc->exponentials += 1;
+  acc->substeps += ns;
+  acc->planned += (int64_t)m * ns;
+  acc->max_m = std::max(acc->max_m, m);
+  acc->max_s = std::max(acc->max_s, ns);
+  acc->max_bound = std::max(acc->max_bound, P.lp.bound);
+  return MAGNUS_OK;
+}
+
+int begin_call(magnus_ctx* ctx, hipStream_t s) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(magnus::launch_slot_reset(ctx->slots, 1, s));
+  return MAGNUS_OK;
+}
+
+int end_call(magnus_ctx* ctx, const Acc& acc, double tol_e, magnus_stats* st, hipStream_t s) {
+  if (!st) return MAGNUS_OK;
+  Slot hs;
+  HIP_TRY(hipMemcpyAsync(&hs, ctx->slots, sizeof(Slot), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  st->exponentials = acc.exponentials;
+  st->substeps = acc.substeps;
+  st->planned_iters = acc.planned;
+  st->iters = hs.iters_total;
+  st->hv_products = hs.iters_total * acc.products_per_iter;
+  st->max_degree_used = acc.max_m;
+  st->max_substeps_used = acc.max_s;
+  st->max_err_bound = acc.max_bound;
+  st->tol_per_exp = tol_e;
+  if (hs.status & 1) return fail(MAGNUS_ENAN, "non-finite vector norm met during the call");
+  return MAGNUS_OK;
+}
+
+double per_exp_tol(const magnus_leja_opts* o, int64_t exps_per_state) {
+  if (o->tol_mode == 1 && exps_per_state > 0) return o->tol / (double)exps_per_state;
+  return o->tol;
+}
+
+// One step of Method Cf4 on one state: the right factor exp(tau(alpha2 A1 + alpha1 A2)) first.
+int cf4_state(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1, double f2,
+              const double2* in, double2* out, double tol_e, const magnus_leja_opts* o, Acc* acc,
+              hipStream_t s) {
+  const double beta = magnus::kAlpha2 * f1 + magnus::kAlpha1 * f2;
+  const double gamma = magnus::kAlpha1 * f1 + magnus::kAlpha2 * f2;
+  double2* mid = ctx->vec(kS2);
+  int rc = run_exponential(ctx, ExpOp{h, 0.5, beta, 0.0}, tau, in, mid, tol_e, o, acc, s);
+  if (rc) return rc;
+  return run_exponential(ctx, ExpOp{h, 0.5, gamma, 0.0}, tau, mid, out, tol_e, o, acc, s);
+}
+
+// One step of Method M4 on one state: exp(-i tau (H1 + fbar H2 + kappa K)).
+int m4_state(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1, double f2,
+             const double2* in, double2* out, double tol_e, const magnus_leja_opts* o, Acc* acc,
+             hipStream_t s) {
+  const double fbar = 0.5 * (f1 + f2);
+  const double kappa = magnus::kSqrt3 * tau * (f2 - f1) / 12.0;
+  return run_exponential(ctx, ExpOp{h, 1.0, fbar, kappa}, tau, in, out, tol_e, o, acc, s);
+}
+
+int check_batch(magnus_ctx* ctx, int32_t batch) {
+  if (batch < 1) return fail(MAGNUS_EINVAL, "batch %d < 1", batch);
+  if (batch > ctx->max_batch) return fail(MAGNUS_ENOMEM, "batch %d exceeds workspace max_batch %d", batch, ctx->max_batch);
+  return MAGNUS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* magnus_last_error(void) { return g_err.c_str(); }
+
+int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t device) {
+  if (!out) return fail(MAGNUS_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (max_dim < 1 || max_batch < 1) return fail(MAGNUS_EINVAL, "max_dim and max_batch must be >= 1");
+  if (max_dim > INT32_MAX / 2) return fail(MAGNUS_EINVAL, "max_dim too large");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(MAGNUS_EINVAL, "device %d not in 0..%d", device, ndev - 1);
+  HIP_TRY(hipSetDevice(device));
+  magnus_ctx* c = new magnus_ctx();
+  c->device = device;
+  c->max_dim = max_dim;
+  c->max_batch = max_batch;
+  c->max_grid = max_dim / 8 + 2;  // the smallest row block of any iteration kernel is 8 rows
+  c->scan_len = 2 * (max_dim / 4 + 2) + 3 * (max_dim / 256 + 2);
+  hipError_t e = hipMalloc(&c->vecs, sizeof(double2) * (size_t)kNumVec * (size_t)max_dim);
+  if (e == hipSuccess) e = hipMalloc(&c->slots, sizeof(Slot));
+  if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * 2 * (size_t)c->max_grid);
+  if (e == hipSuccess) e = hipMalloc(&c->scan, sizeof(double) * (size_t)c->scan_len);
+  if (e == hipSuccess) e = hipMemset(c->slots, 0, sizeof(Slot));
+  if (e == hipSuccess) e = hipMemset(c->vecs, 0, sizeof(double2) * (size_t)kNumVec * (size_t)max_dim);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    magnus_destroy(c);
+    return fail(MAGNUS_EHIP, "workspace allocation: %s", hipGetErrorString(e));
+  }
+  (void)magnus::leja_points();  // build the planner tables once, up front
+  *out = c;
+  return MAGNUS_OK;
+}
+
+int magnus_destroy(magnus_ctx* ctx) {
+  if (!ctx) return MAGNUS_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->vecs) (void)hipFree(ctx->vecs);
+  if (ctx->slots) (void)hipFree(ctx->slots);
+  if (ctx->partials) (void)hipFree(ctx->partials);
+  if (ctx->scan) (void)hipFree(ctx->scan);
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return MAGNUS_OK;
+}
+
+int magnus_check(magnus_ctx* ctx, magnus_stream stream) {
+  if (!ctx) return fail(MAGNUS_EINVAL, "null context");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  Slot hs;
+  HIP_TRY(hipMemcpyAsync(&hs, ctx->slots, sizeof(Slot), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hs.status & 1) return fail(MAGNUS_ENAN, "non-finite vector norm met on the device");
+  return MAGNUS_OK;
+}
+
+int magnus_spectral_bounds(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream) {
+  if (!ctx || !h) return fail(MAGNUS_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int64_t dim = h->H1.dim;
+  if (dim < 1 || dim > ctx->max_dim) return fail(dim < 1 ? MAGNUS_EINVAL : MAGNUS_ENOMEM, "dim %lld", (long long)dim);
+  magnus_term* terms[2] = {&h->H1, &h->H2};
+  for (magnus_term* t : terms) {
+    // the enclosure is not yet known: validate the rest of the term only
+    const double l0 = t->lam_min, u0 = t->lam_max;
+    t->lam_min = 0.0;
+    t->lam_max = 0.0;
+    int rc = check_term(*t, dim, t == &h->H1 ? "H1" : "H2");
+    t->lam_min = l0;
+    t->lam_max = u0;
+    if (rc) return rc;
+    double lo, hi;
+    rc = (t->format == MAGNUS_CSR) ? csr_scan(ctx, *t, s, &lo, &hi) : dense_scan(ctx, *t, s, &lo, &hi);
+    if (rc) return rc;
+    t->lam_min = lo;
+    t->lam_max = hi;
+  }
+  const double n1 = std::fmax(std::fabs(h->H1.lam_min), std::fabs(h->H1.lam_max));
+  const double n2 = std::fmax(std::fabs(h->H2.lam_min), std::fabs(h->H2.lam_max));
+  h->k_min = -2.0 * n1 * n2;
+  h->k_max = 2.0 * n1 * n2;
+  return MAGNUS_OK;
+}
+
+int expmv_leja(magnus_ctx* ctx, const magnus_hamiltonian* h, double a, double b, double kappa, double tau,
+               const void* v, void* w, int32_t batch, const magnus_leja_opts* opts, magnus_stats* stats,
+               magnus_stream stream) {
+  int rc = check_ham(ctx, h, kappa != 0.0);
+  if (rc) return rc;
+  if ((rc = check_opts(opts)) || (rc = check_batch(ctx, batch))) return rc;
+  if (!v || !w) return fail(MAGNUS_EINVAL, "null state pointer");
+  if (!is_fin(a) || !is_fin(b) || !is_fin(kappa) || !is_fin(tau))
+    return fail(MAGNUS_EDOMAIN, "non-finite coefficient or step");
+  if (kappa != 0.0 && h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "commutator exponents need CSR terms");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = begin_call(ctx, s))) return rc;
+  if ((rc = ensure_valid(ctx, h, s))) return rc;
+  const int64_t dim = h->H1.dim;
+  const double tol_e = per_exp_tol(opts, 1);
+  Acc acc;
+  acc.products_per_iter = kappa != 0.0 ? 4 : 2;
+  const double2* vin = reinterpret_cast<const double2*>(v);
+  double2* wout = reinterpret_cast<double2*>(w);
+  for (int32_t c = 0; c < batch; ++c) {
+    rc = run_exponential(ctx, ExpOp{h, a, b, kappa}, tau, vin + c * dim, wout + c * dim, tol_e, opts, &acc, s);
+    if (rc) return rc;
+  }
+  return end_call(ctx, acc, tol_e, stats, s);
+}
+
+static int step_common(int method, magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1,
+                       double f2, const void* psi_in, void* psi_out, int32_t batch,
+                       const magnus_leja_opts* opts, magnus_stats* stats, magnus_stream stream) {
+  int rc = check_ham(ctx, h, method == MAGNUS_M4);
+  if (rc) return rc;
+  if ((rc = check_opts(opts)) || (rc = check_batch(ctx, batch))) return rc;
+  if (!psi_in || !psi_out) return fail(MAGNUS_EINVAL, "null state pointer");
+  if (!is_fin(tau) || !is_fin(f1) || !is_fin(f2)) return fail(MAGNUS_EDOMAIN, "non-finite step or field value");
+  if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "M4 needs CSR terms");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = begin_call(ctx, s))) return rc;
+  if ((rc = ensure_valid(ctx, h, s))) return rc;
+  const int64_t dim = h->H1.dim;
+  const double tol_e = per_exp_tol(opts, method == MAGNUS_CF4 ? 2 : 1);
+  Acc acc;
+  acc.products_per_iter = method == MAGNUS_M4 ? 4 : 2;
+  const double2* in = reinterpret_cast<const double2*>(psi_in);
+  double2* out = reinterpret_cast<double2*>(psi_out);
+  for (int32_t c = 0; c < batch; ++c) {
+    rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s)
+                                : m4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s);
+    if (rc) return rc;
+  }
+  return end_call(ctx, acc, tol_e, stats, s);
+}
+
+int magnus_step_cf4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1, double f2,
+                    const void* psi_in, void* psi_out, int32_t batch, const magnus_leja_opts* opts,
+                    magnus_stats* stats, magnus_stream stream) {
+  return step_common(MAGNUS_CF4, ctx, h, tau, f1, f2, psi_in, psi_out, batch, opts, stats, stream);
+}
+
+int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1, double f2,
+                   const void* psi_in, void* psi_out, int32_t batch, const magnus_leja_opts* opts,
+                   magnus_stats* stats, magnus_stream stream) {
+  return step_common(MAGNUS_M4, ctx, h, tau, f1, f2, psi_in, psi_out, batch, opts, stats, stream);
+}
+
+int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, double tau, int64_t nsteps,
+              const double* f_nodes, int32_t batch_f, void* psi, int32_t batch, void* checkpoints,
+              int32_t every_k, const magnus_leja_opts* opts, magnus_stats* stats, magnus_stream stream) {
+  if (method != MAGNUS_CF4 && method != MAGNUS_M4) return fail(MAGNUS_EINVAL, "unknown method %d", method);
+  int rc = check_ham(ctx, h, method == MAGNUS_M4);
+  if (rc) return rc;
+  if ((rc = check_opts(opts)) || (rc = check_batch(ctx, batch))) return rc;
+  if (!psi) return fail(MAGNUS_EINVAL, "null state pointer");
+  if (nsteps < 0) return fail(MAGNUS_EINVAL, "nsteps %lld < 0", (long long)nsteps);
+  if (nsteps > 0 && !f_nodes) return fail(MAGNUS_EINVAL, "null f_nodes");
+  if (batch_f != 1 && batch_f != batch) return fail(MAGNUS_EINVAL, "batch_f %d must be 1 or batch", batch_f);
+  if (checkpoints && every_k < 1) return fail(MAGNUS_EINVAL, "every_k %d < 1", every_k);
+  if (!is_fin(tau)) return fail(MAGNUS_EDOMAIN, "non-finite step");
+  for (int64_t k = 0; k < 2 * nsteps * (int64_t)batch_f; ++k)
+    if (!is_fin(f_nodes[k])) return fail(MAGNUS_EDOMAIN, "non-finite field value at node %lld", (long long)k);
+  if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "M4 needs CSR terms");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = begin_call(ctx, s))) return rc;
+  if ((rc = ensure_valid(ctx, h, s))) return rc;
+  const int64_t dim = h->H1.dim;
+  const int64_t exps = (method == MAGNUS_CF4 ? 2 : 1) * nsteps;
+  const double tol_e = per_exp_tol(opts, exps);
+  Acc acc;
+  acc.products_per_iter = method == MAGNUS_M4 ? 4 : 2;
+  double2* st = reinterpret_cast<double2*>(psi);
+  double2* ck = reinterpret_cast<double2*>(checkpoints);
+  const int64_t nck = checkpoints ? (nsteps + every_k - 1) / every_k + 1 : 0;
+  const size_t stride = (size_t)dim * (size_t)batch;
+  if (ck) HIP_TRY(hipMemcpyAsync(ck, st, sizeof(double2) * stride, hipMemcpyDeviceToDevice, s));
+  for (int64_t n = 0; n < nsteps; ++n) {
+    for (int32_t c = 0; c < batch; ++c) {
+      const double* fn = f_nodes + ((batch_f == 1 ? 0 : (int64_t)c) * nsteps + n) * 2;
+      double2* y = st + c * dim;
+      rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, fn[0], fn[1], y, y, tol_e, opts, &acc, s)
+                                  : m4_state(ctx, h, tau, fn[0], fn[1], y, y, tol_e, opts, &acc, s);
+      if (rc) return rc;
+    }
+    if (ck && ((n + 1) % every_k == 0 || n + 1 == nsteps)) {
+      const int64_t slot = (n + 1) % every_k == 0 ? (n + 1) / every_k : nck - 1;
+      HIP_TRY(hipMemcpyAsync(ck + slot * stride, st, sizeof(double2) * stride, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  return end_call(ctx, acc, tol_e, stats, s);
+}
+
+int magnus_timing(magnus_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(MAGNUS_EINVAL, "null context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (enable) {
+    HIP_TRY(hipDeviceSynchronize());  // pooled events may still be pending
+    ctx->records.clear();
+    ctx->pool_used = 0;
+  }
+  ctx->timing = enable != 0;
+  return MAGNUS_OK;
+}
+
+int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return fail(MAGNUS_EINVAL, "null argument");
+  if (kind < MAGNUS_KERNEL_CSR_LEJA || kind > MAGNUS_KERNEL_DENSE_LEJA) return fail(MAGNUS_EINVAL, "kernel class %d", kind);
+  HIP_TRY(hipSetDevice(ctx->device));
+  double t = 0.0;
+  int64_t n = 0;
+  for (auto& r : ctx->records) {
+    if (std::get<0>(r) != kind) continue;
+    HIP_TRY(hipEventSynchronize(std::get<2>(r)));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, std::get<1>(r), std::get<2>(r)));
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return MAGNUS_OK;
+}
+
+int magnus_quadrature_nodes(int32_t method, double t0, double tau, int64_t nsteps, double* t_out) {
+  if (method != MAGNUS_CF4 && method != MAGNUS_M4) return fail(MAGNUS_EINVAL, "unknown method %d", method);
+  if (nsteps < 0 || (nsteps > 0 && !t_out)) return fail(MAGNUS_EINVAL, "bad output");
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const double tn = t0 + (double)n * tau;
+    t_out[2 * n] = tn + magnus::kC1 * tau;
+    t_out[2 * n + 1] = tn + magnus::kC2 * tau;
+  }
+  return MAGNUS_OK;
+}
+
+int magnus_leja_points(int32_t m, double* xi) {
+  if (m < 0 || m >= magnus::kNumPoints || !xi) return fail(MAGNUS_EINVAL, "m %d outside 0..%d", m, magnus::kNumPoints - 1);
+  const auto& p = magnus::leja_points();
+  for (int k = 0; k <= m; ++k) xi[k] = p[k];
+  return MAGNUS_OK;
+}
+
+int magnus_divided_differences(double theta, int32_t m, double* d) {
+  if (m < 0 || m >= magnus::kNumPoints || !d) return fail(MAGNUS_EINVAL, "m %d outside 0..%d", m, magnus::kNumPoints - 1);
+  if (!is_fin(theta) || std::fabs(theta) > magnus::kThetaCap)
+    return fail(MAGNUS_EDOMAIN, "|theta| %g above %g", theta, magnus::kThetaCap);
+  std::vector<std::complex<double>> v(m + 1);
+  magnus::divided_differences(theta, m, v.data());
+  for (int k = 0; k <= m; ++k) { d[2 * k] = v[k].real(); d[2 * k + 1] = v[k].imag(); }
+  return MAGNUS_OK;
+}
+
+double magnus_leja_error(double theta, int32_t m) {
+  if (!is_fin(theta) || std::fabs(theta) > magnus::kThetaCap) return INFINITY;
+  return magnus::leja_error(theta, m);
+}
+
+int magnus_leja_plan(double theta, double tol, int32_t max_degree, int32_t max_substeps, int32_t* m, int32_t* s,
+                     double* bound) {
+  if (!m || !s || !bound) return fail(MAGNUS_EINVAL, "null output");
+  if (!(tol > 0.0) || !is_fin(theta)) return fail(MAGNUS_EDOMAIN, "bad theta or tol");
+  magnus::LejaPlan p;
+  if (!magnus::plan_degree(theta, tol, max_degree, max_substeps, &p))
+    return fail(MAGNUS_ENOCONV, "caps cannot reach tol %g at theta %g", tol, theta);
+  *m = p.m;
+  *s = p.s;
+  *bound = p.bound;
+  return MAGNUS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal device-side interface of libmagnus: kernel launchers used by the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace magnus {
+
+// Per-state control block in device memory.  One Leja substep runs as a
+// sequence of iteration kernels; the last workgroup of each iteration reduces
+// the norm partials in a fixed order, evaluates the early-termination test and
+// writes the verdict here for the next iteration to read.
+struct Slot {
+  unsigned int counter;   // workgroups of the current kernel that have finished
+  int stopped;            // 1: the current substep has terminated early
+  int iters_sub;          // iterations done in the current substep
+  int status;             // sticky: bit 0 = non-finite norm seen
+  long long iters_total;  // sticky: Leja iterations executed since the last reset
+  double vnorm;           // |v| of the current substep
+  double prev_term;       // |d_{i-1}| |w_{i-1}|
+  double last_est;        // last early-termination estimate
+};
+
+struct CsrDev {
+  const int* rp;
+  const int* ci;
+  const double2* val;
+};
+
+enum IterMode : int {
+  kLeja = 0,       // y = a1 H1 x1 + a2 H2 x2, then the Leja update
+  kSplit = 1,      // out1 = H1 x1, out2 = H2 x2 (first half of a commutator pass)
+  kLejaComm = 2,   // y = a1 x2 + a2 x1 + i k (H1 x1 - H2 x2), then the Leja update
+};
+
+// One Leja iteration: w_i = X w_{i-1} - xi_{i-1} w_{i-1}, p += d_i w_i, where
+// X w = a1 (H1 w) + a2 (H2 w) [+ k K w] - c' w has been folded into the
+// coefficients below (sigma = scale * c + xi_{i-1}).
+struct IterArgs {
+  const double2* x1;    // vector gathered by term 1
+  const double2* x2;    // vector gathered by term 2
+  const double2* wcur;  // w_{i-1} (own rows); v for the first iteration
+  double2* wout;        // w_i            (kSplit: H1 x1)
+  double2* pacc;        // p accumulator  (kSplit: H2 x2)
+  Slot* slot;
+  double* partials;     // 2 * grid doubles
+  double a1, a2, kap;
+  double sigma;
+  double2 d;            // d_i
+  double2 d0;           // d_0 (first iteration)
+  double dabs;          // |d_i|
+  double d0abs;         // |d_0|
+  double tol;           // early-termination threshold relative to |v|
+  int early;            // early termination enabled
+  int first;            // first iteration of a substep
+  int check_stop;       // return at once if the substep has stopped
+};
+
+// Launch one iteration over `dim` rows of the two CSR terms.
+hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int dim,
+                            const IterArgs& a, int rows_per_block, hipStream_t s);
+
+// Grid size (workgroups) of launch_csr2_iter for `dim` rows.
+int csr2_grid(int dim, int rows_per_block);
+
+// Gershgorin enclosure and structural check of one CSR term.  Writes per
+// workgroup min, max and a "malformed" flag into out[3 * grid].
+hipError_t launch_csr_gershgorin(const CsrDev& t, int dim, long long nnz, double* out, int grid,
+                                 hipStream_t s);
+int csr_gershgorin_grid(int dim);
+
+// Gershgorin enclosure of a dense row-major term (out[2 * grid]).
+hipError_t launch_dense_gershgorin(const double2* H, int dim, long long ld, double* out, int grid,
+                                   hipStream_t s);
+int dense_gershgorin_grid(int dim);
+
+// Dense two-term Leja iteration (mode kLeja only).
+hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
+                              const IterArgs& a, hipStream_t s);
+int dense2_grid(int dim);
+
+// Small helpers.
+hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_t s);
+hipError_t launch_slot_reset(Slot* slot, int n, hipStream_t s);
+
+}  // namespace magnus

@@ -1,0 +1,433 @@
+// HIP kernels of libmagnus for gfx950 (CDNA4, wave64).
+//
+// The hot loop is one Leja iteration (Section 3, the Newton-form recurrence
+// w <- A w - xi_{i-1} w, p <- p + d_i w), fused into a single pass over the
+// Hamiltonian: the matrix-vector product of both terms of H(t) = H1 + f H2
+// (Section 4), the shift, the accumulation into p, and the partial sums of
+// |w_i|^2 (and |v|^2 on the first iteration) for the error control.  The last
+// workgroup to finish reduces the partials in a fixed order and writes the
+// early-termination verdict for the next iteration, so the host never waits.
+#include "kernels.h"
+
+#include <cmath>
+
+namespace magnus {
+namespace {
+
+using d2 = double __attribute__((ext_vector_type(2)));
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ d2 cmul(d2 a, d2 b) {
+  return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ d2 rmul(double s, d2 a) { return d2{s * a.x, s * a.y}; }
+__device__ __forceinline__ d2 tod2(double2 v) { return d2{v.x, v.y}; }
+__device__ __forceinline__ double2 fromd2(d2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double nrm2(d2 v) { return v.x * v.x + v.y * v.y; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of row blocks so rows that share gathered vector entries
+// share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+  return x * q + min(x, rem) + k;
+}
+
+__device__ __forceinline__ int load_stopped(const Slot* s) {
+  return __hip_atomic_load(&s->stopped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Leja update for one row; y = (scale-folded) H_hat w at that row.
+__device__ __forceinline__ void leja_row(const IterArgs& a, int r, d2 y, double& pw, double& pv) {
+  const d2 w_old = tod2(a.wcur[r]);
+  const d2 wn = y - rmul(a.sigma, w_old);
+  d2 p;
+  if (a.first) {
+    p = cmul(tod2(a.d0), w_old) + cmul(tod2(a.d), wn);
+    pv += nrm2(w_old);
+  } else {
+    p = tod2(a.pacc[r]) + cmul(tod2(a.d), wn);
+  }
+  a.wout[r] = fromd2(wn);
+  a.pacc[r] = fromd2(p);
+  pw += nrm2(wn);
+}
+
+// Block reduction of the norm partials, then the last-workgroup decision.
+__device__ void finish_iteration(const IterArgs& a, double pw, double pv) {
+  __shared__ double red[2][kThreads / 64];
+  __shared__ int amlast;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  pw = wave_sum(pw);
+  pv = wave_sum(pv);
+  if (lane == 0) { red[0][wv] = pw; red[1][wv] = pv; }
+  __syncthreads();
+  if (tid == 0) {
+    double bw = 0.0, bv = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) { bw += red[0][w]; bv += red[1][w]; }
+    a.partials[2 * blockIdx.x] = bw;
+    a.partials[2 * blockIdx.x + 1] = bv;
+    __threadfence();
+    const unsigned prev = atomicAdd(&a.slot->counter, 1u);
+    amlast = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!amlast) return;
+  __threadfence();
+  double sw = 0.0, sv = 0.0;
+  for (int k = tid; k < (int)gridDim.x; k += kThreads) {
+    sw += __hip_atomic_load(&a.partials[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sv += __hip_atomic_load(&a.partials[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  sw = wave_sum(sw);
+  sv = wave_sum(sv);
+  __syncthreads();
+  if (lane == 0) { red[0][wv] = sw; red[1][wv] = sv; }
+  __syncthreads();
+  if (tid == 0) {
+    double tw = 0.0, tv = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) { tw += red[0][w]; tv += red[1][w]; }
+    Slot* S = a.slot;
+    const double wn = sqrt(tw);
+    const double vn = a.first ? sqrt(tv) : S->vnorm;
+    const double prev = a.first ? a.d0abs * vn : S->prev_term;
+    const double term = a.dabs * wn;
+    const double est = term + prev;
+    const bool bad = !isfinite(tw) || !isfinite(vn);
+    if (bad) S->status |= 1;
+    S->vnorm = vn;
+    S->prev_term = term;
+    S->last_est = est;
+    S->iters_sub = a.first ? 1 : S->iters_sub + 1;
+    S->stopped = (bad || (a.early && est <= a.tol * vn)) ? 1 : 0;
+    S->iters_total += 1;
+    __threadfence();
+    S->counter = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-term CSR iteration.  A workgroup owns ROWS consecutive rows; all of its
+// threads stream the rows' nonzeros of both terms (coalesced, non-temporal,
+// so the gathered vectors keep the caches), multiply by the gathered vector
+// entries and stage the products in LDS; then LPR threads per row sum the
+// row's products in a fixed order.  Any nonzero distribution is handled by
+// processing the workgroup's nonzeros in chunks of CAP.
+// ---------------------------------------------------------------------------
+template <int ROWS, int MODE>
+__global__ __launch_bounds__(kThreads) void csr2_iter_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+  constexpr int LPR = kThreads / ROWS;
+  constexpr int CAP = ROWS * 32;
+  constexpr int U = 4;
+  __shared__ d2 prod[CAP];
+  __shared__ int rps[2][ROWS + 1];
+  if (a.check_stop && load_stopped(a.slot)) return;
+
+  const int tid = threadIdx.x;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int row0 = L * ROWS;
+  const int nrows = min(ROWS, dim - row0);
+  if (tid <= nrows) rps[0][tid] = t1.rp[row0 + tid];
+  if (tid >= 128 && tid - 128 <= nrows) rps[1][tid - 128] = t2.rp[row0 + tid - 128];
+  __syncthreads();
+  const int base1 = rps[0][0], n1 = rps[0][nrows] - base1;
+  const int base2 = rps[1][0], n2 = rps[1][nrows] - base2;
+  const int total = n1 + n2;
+  const int rr = tid / LPR, q = tid % LPR;
+  int s1 = 0, e1 = 0, s2 = 0, e2 = 0;
+  if (rr < nrows) {
+    s1 = rps[0][rr] - base1;
+    e1 = rps[0][rr + 1] - base1;
+    s2 = n1 + rps[1][rr] - base2;
+    e2 = n1 + rps[1][rr + 1] - base2;
+  }
+  const d2* x1 = reinterpret_cast<const d2*>(a.x1);
+  const d2* x2 = reinterpret_cast<const d2*>(a.x2);
+  const d2* v1 = reinterpret_cast<const d2*>(t1.val);
+  const d2* v2 = reinterpret_cast<const d2*>(t2.val);
+  d2 acc1 = {0.0, 0.0}, acc2 = {0.0, 0.0};
+
+  for (int c0 = 0; c0 < total; c0 += CAP) {
+    const int cn = min(CAP, total - c0);
+    for (int kb = 0; kb < cn; kb += kThreads * U) {
+      int col[U];
+      d2 val[U];
+      bool in1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = kb + u * kThreads + tid;
+        const int g = c0 + k;
+        in1[u] = g < n1;
+        col[u] = 0;
+        val[u] = d2{0.0, 0.0};
+        if (k < cn) {
+          if (in1[u]) {
+            col[u] = __builtin_nontemporal_load(t1.ci + base1 + g);
+            val[u] = __builtin_nontemporal_load(v1 + base1 + g);
+          } else {
+            col[u] = __builtin_nontemporal_load(t2.ci + base2 + (g - n1));
+            val[u] = __builtin_nontemporal_load(v2 + base2 + (g - n1));
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = kb + u * kThreads + tid;
+        if (k < cn) {
+          const d2 x = in1[u] ? x1[col[u]] : x2[col[u]];
+          prod[k] = cmul(val[u], x);
+        }
+      }
+    }
+    __syncthreads();
+    if (rr < nrows) {
+      const int hi = c0 + cn;
+      for (int k = max(s1, c0) + q; k < min(e1, hi); k += LPR) acc1 += prod[k - c0];
+      for (int k = max(s2, c0) + q; k < min(e2, hi); k += LPR) acc2 += prod[k - c0];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) {
+    acc1.x += __shfl_xor(acc1.x, off, 64);
+    acc1.y += __shfl_xor(acc1.y, off, 64);
+    acc2.x += __shfl_xor(acc2.x, off, 64);
+    acc2.y += __shfl_xor(acc2.y, off, 64);
+  }
+  const bool owner = (q == 0) && (rr < nrows);
+  const int r = row0 + rr;
+  if constexpr (MODE == kSplit) {
+    if (owner) {
+      a.wout[r] = fromd2(acc1);
+      a.pacc[r] = fromd2(acc2);
+    }
+    return;
+  } else {
+    double pw = 0.0, pv = 0.0;
+    if (owner) {
+      d2 y;
+      if constexpr (MODE == kLeja) {
+        y = rmul(a.a1, acc1) + rmul(a.a2, acc2);
+      } else {
+        const d2 Ur = x2[r], Vr = x1[r];
+        const d2 dl = acc1 - acc2;
+        y = rmul(a.a1, Ur) + rmul(a.a2, Vr) + d2{-a.kap * dl.y, a.kap * dl.x};
+      }
+      leja_row(a, r, y, pw, pv);
+    }
+    finish_iteration(a, pw, pv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-term dense iteration (row-major H1, H2).  A wave owns RPW rows; its
+// lanes stride over columns so every matrix load is a coalesced 1 KiB
+// transaction, and each gathered x_j is loaded once per lane for RPW rows and
+// both terms.
+// ---------------------------------------------------------------------------
+template <int RPW>
+__global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1, const double2* H2,
+                                                              int dim, long long ld, IterArgs a) {
+  if (a.check_stop && load_stopped(a.slot)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int rbase = (L * (kThreads / 64) + wv) * RPW;
+  const d2* x = reinterpret_cast<const d2*>(a.x1);
+  const d2* A1 = reinterpret_cast<const d2*>(H1);
+  const d2* A2 = reinterpret_cast<const d2*>(H2);
+  d2 acc1[RPW], acc2[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) { acc1[r] = d2{0.0, 0.0}; acc2[r] = d2{0.0, 0.0}; }
+  int nr = min(RPW, dim - rbase);
+  if (nr < 0) nr = 0;
+#pragma unroll 2
+  for (int j = lane; j < dim; j += 64) {
+    const d2 xj = x[j];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (r < nr) {
+        const long long off = (long long)(rbase + r) * ld + j;
+        acc1[r] += cmul(__builtin_nontemporal_load(A1 + off), xj);
+        acc2[r] += cmul(__builtin_nontemporal_load(A2 + off), xj);
+      }
+    }
+  }
+  double pw = 0.0, pv = 0.0;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    d2 s1 = acc1[r], s2 = acc2[r];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1.x += __shfl_xor(s1.x, off, 64);
+      s1.y += __shfl_xor(s1.y, off, 64);
+      s2.x += __shfl_xor(s2.x, off, 64);
+      s2.y += __shfl_xor(s2.y, off, 64);
+    }
+    if (lane == r && r < nr) {
+      const d2 y = rmul(a.a1, s1) + rmul(a.a2, s2);
+      leja_row(a, rbase + r, y, pw, pv);
+    }
+  }
+  finish_iteration(a, pw, pv);
+}
+
+// ---------------------------------------------------------------------------
+// Gershgorin discs + structure check (CSR), one thread per row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void csr_gershgorin_kernel(CsrDev t, int dim, long long nnz,
+                                                                double* out) {
+  __shared__ double smin[kThreads], smax[kThreads];
+  __shared__ int sbad[kThreads];
+  const int tid = threadIdx.x;
+  const int r = blockIdx.x * kThreads + tid;
+  double lo = INFINITY, hi = -INFINITY;
+  int bad = 0;
+  if (r < dim) {
+    const long long rs = t.rp[r], re = t.rp[r + 1];
+    if (r == 0 && rs != 0) bad = 1;
+    if (r == dim - 1 && re != nnz) bad = 1;
+    if (rs < 0 || re < rs || re > nnz) bad = 1;
+    double diag = 0.0, rad = 0.0;
+    if (!bad) {
+      for (long long j = rs; j < re; ++j) {
+        const int c = t.ci[j];
+        const double2 v = t.val[j];
+        if (c < 0 || c >= dim) { bad = 1; break; }
+        if (c == r) { diag += v.x; rad += fabs(v.y); }
+        else rad += sqrt(v.x * v.x + v.y * v.y);
+      }
+    }
+    lo = diag - rad;
+    hi = diag + rad;
+  }
+  smin[tid] = lo; smax[tid] = hi; sbad[tid] = bad;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      smin[tid] = fmin(smin[tid], smin[tid + s]);
+      smax[tid] = fmax(smax[tid], smax[tid + s]);
+      sbad[tid] |= sbad[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[3 * blockIdx.x] = smin[0];
+    out[3 * blockIdx.x + 1] = smax[0];
+    out[3 * blockIdx.x + 2] = (double)sbad[0];
+  }
+}
+
+// Gershgorin discs of a dense row-major term, one wave per row.
+__global__ __launch_bounds__(kThreads) void dense_gershgorin_kernel(const double2* H, int dim, long long ld,
+                                                                  double* out) {
+  __shared__ double smin[kThreads / 64], smax[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = blockIdx.x * (kThreads / 64) + wv;
+  double lo = INFINITY, hi = -INFINITY;
+  if (r < dim) {
+    double rad = 0.0, diag = 0.0;
+    for (int j = lane; j < dim; j += 64) {
+      const double2 v = H[(long long)r * ld + j];
+      if (j == r) { diag += v.x; rad += fabs(v.y); }
+      else rad += sqrt(v.x * v.x + v.y * v.y);
+    }
+    rad = wave_sum(rad);
+    diag = wave_sum(diag);
+    lo = diag - rad;
+    hi = diag + rad;
+  }
+  if (lane == 0) { smin[wv] = lo; smax[wv] = hi; }
+  __syncthreads();
+  if (tid == 0) {
+    double a = INFINITY, b = -INFINITY;
+    for (int w = 0; w < kThreads / 64; ++w) { a = fmin(a, smin[w]); b = fmax(b, smax[w]); }
+    out[2 * blockIdx.x] = a;
+    out[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ void copy_kernel(const double2* __restrict__ src, double2* __restrict__ dst, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void slot_reset_kernel(Slot* s, int n) {
+  const int i = threadIdx.x;
+  if (i < n) {
+    s[i].counter = 0u;
+    s[i].stopped = 0;
+    s[i].iters_sub = 0;
+    s[i].status = 0;
+    s[i].iters_total = 0;
+    s[i].vnorm = 0.0;
+    s[i].prev_term = 0.0;
+    s[i].last_est = 0.0;
+  }
+}
+
+}  // namespace
+
+int csr2_grid(int dim, int rows_per_block) { return (dim + rows_per_block - 1) / rows_per_block; }
+
+hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a,
+                            int rows_per_block, hipStream_t s) {
+  const int grid = csr2_grid(dim, rows_per_block);
+#define MAGNUS_CSR_CASE(R, M) \
+  if (rows_per_block == R && mode == M) { csr2_iter_kernel<R, M><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); return hipGetLastError(); }
+  MAGNUS_CSR_CASE(64, kLeja)
+  MAGNUS_CSR_CASE(64, kSplit)
+  MAGNUS_CSR_CASE(64, kLejaComm)
+  MAGNUS_CSR_CASE(16, kLeja)
+  MAGNUS_CSR_CASE(16, kSplit)
+  MAGNUS_CSR_CASE(16, kLejaComm)
+#undef MAGNUS_CSR_CASE
+  return hipErrorInvalidValue;
+}
+
+int csr_gershgorin_grid(int dim) { return (dim + kThreads - 1) / kThreads; }
+
+hipError_t launch_csr_gershgorin(const CsrDev& t, int dim, long long nnz, double* out, int grid, hipStream_t s) {
+  csr_gershgorin_kernel<<<grid, kThreads, 0, s>>>(t, dim, nnz, out);
+  return hipGetLastError();
+}
+
+int dense_gershgorin_grid(int dim) { return (dim + kThreads / 64 - 1) / (kThreads / 64); }
+
+hipError_t launch_dense_gershgorin(const double2* H, int dim, long long ld, double* out, int grid,
+                                   hipStream_t s) {
+  dense_gershgorin_kernel<<<grid, kThreads, 0, s>>>(H, dim, ld, out);
+  return hipGetLastError();
+}
+
+constexpr int kDenseRPW = 2;
+int dense2_grid(int dim) {
+  const int rows_per_block = kDenseRPW * (kThreads / 64);
+  return (dim + rows_per_block - 1) / rows_per_block;
+}
+
+hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
+                              const IterArgs& a, hipStream_t s) {
+  dense2_iter_kernel<kDenseRPW><<<dense2_grid(dim), kThreads, 0, s>>>(H1, H2, dim, ld, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long grid = (n + kThreads - 1) / kThreads;
+  copy_kernel<<<(unsigned)grid, kThreads, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_reset(Slot* slot, int n, hipStream_t s) {
+  slot_reset_kernel<<<1, 64, 0, s>>>(slot, n);
+  return hipGetLastError();
+}
+
+}  // namespace magnus

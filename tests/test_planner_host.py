@@ -1,0 +1,140 @@
+"""Host logic of libmagnus on the CPU: exports, Leja points, divided
+differences, a priori error, degree/substep plans, quadrature nodes.
+
+These call only pure host functions of the library (no device is touched).
+"""
+import math
+import os
+import re
+
+import mpmath
+import numpy as np
+import pytest
+
+from paper_1709_06483_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_header_symbol():
+    L = B.lib()
+    with open(os.path.join(ROOT, "include", "magnus.h")) as fh:
+        text = fh.read()
+    declared = set(re.findall(r"^\s*(?:int|double|const char\*|void)\s+(\w+)\s*\(", text, re.M))
+    assert declared == set(B.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_leja_points_first_values():
+    xi = B.magnus_leja_points(8)
+    assert xi[0] == 2.0 and xi[1] == -2.0 and xi[2] == 0.0
+    # maximisers of |x|(4 - x^2): +-2/sqrt(3); the tie goes to the left
+    assert abs(xi[3] + 2 / math.sqrt(3)) < 1e-14
+    assert len(set(np.round(xi, 12))) == 9
+
+
+def test_leja_points_greedy_definition():
+    # brute-force greedy maximisation of prod |x - xi_j| on a fine grid
+    xi = B.magnus_leja_points(30)
+    grid = np.linspace(-2, 2, 400001)
+    for k in range(1, 31):
+        lp = np.sum(np.log(np.abs(grid[:, None] - xi[None, :k]) + 1e-300), axis=1)
+        best = lp.max()
+        own = np.sum(np.log(np.abs(xi[k] - xi[:k])))
+        # the chosen point attains the grid maximum up to grid resolution
+        assert own >= best - 1e-6, (k, own, best)
+
+
+def _mp_divided_differences(theta, pts, dps):
+    with mpmath.workdps(dps):
+        x = [mpmath.mpf(float(p)) for p in pts]
+        f = [mpmath.exp(-1j * mpmath.mpf(theta) * xx) for xx in x]
+        table = list(f)
+        out = [table[0]]
+        for k in range(1, len(x)):
+            table = [(table[i + 1] - table[i]) / (x[i + k] - x[i]) for i in range(len(table) - 1)]
+            out.append(table[0])
+        return [complex(v) for v in out]
+
+
+@pytest.mark.parametrize("theta", [1e-3, 0.05, 0.3, 1.0, 2.5, 4.0, -0.7])
+def test_divided_differences_match_mpmath(theta):
+    m = 30
+    pts = B.magnus_leja_points(m)
+    d = B.magnus_divided_differences(theta, m)
+    ref = _mp_divided_differences(theta, pts, dps=260)
+    for k in range(m + 1):
+        if abs(ref[k]) > 1e-280:
+            assert abs(d[k] - ref[k]) <= 2e-14 * abs(ref[k]) + 1e-300, (k, d[k], ref[k])
+
+
+@pytest.mark.parametrize("theta", [0.01, 0.2, 1.5, 3.9])
+def test_newton_form_interpolates(theta):
+    m = 20
+    pts = B.magnus_leja_points(m)
+    d = B.magnus_divided_differences(theta, m)
+    for j in range(m + 1):
+        x = pts[j]
+        p, basis = 0j, 1.0
+        for k in range(m + 1):
+            p += d[k] * basis
+            basis *= x - pts[k]
+        assert abs(p - np.exp(-1j * theta * x)) < 1e-14
+
+
+@pytest.mark.parametrize("theta,m", [(0.05, 4), (0.12, 7), (0.5, 10), (2.0, 18), (3.5, 20)])
+def test_error_bound_matches_brute_force(theta, m):
+    pts = B.magnus_leja_points(m)
+    d = B.magnus_divided_differences(theta, m)
+    x = np.linspace(-2, 2, 200001)
+    p = np.zeros_like(x, dtype=complex)
+    basis = np.ones_like(x)
+    for k in range(m + 1):
+        p += d[k] * basis
+        basis = basis * (x - pts[k])
+    brute = np.max(np.abs(np.exp(-1j * theta * x) - p))
+    got = B.magnus_leja_error(theta, m)
+    assert brute > 1e-13  # the check is meaningful only above rounding
+    assert abs(got - brute) <= 0.02 * brute, (got, brute)
+
+
+def test_plan_meets_tolerance_and_is_monotone():
+    prev = 0
+    for theta in np.geomspace(1e-4, 3.9, 40):
+        m, s, bound = B.magnus_leja_plan(theta, 1e-12)
+        assert s == 1
+        assert m >= prev
+        prev = m
+        assert bound <= 0.5e-12
+        assert s * B.magnus_leja_error(theta / s, m) <= 0.51e-12
+        if m > 1:  # one degree less would not do
+            assert s * B.magnus_leja_error(theta / s, m - 1) > 0.5e-12 * 0.9
+
+
+def test_plan_substeps_for_large_theta():
+    m, s, bound = B.magnus_leja_plan(20.0, 1e-10)
+    assert s >= 5 and m * s < 400 and bound <= 0.5e-10
+    with pytest.raises(B.MagnusError) as e:
+        B.magnus_leja_plan(20.0, 1e-10, max_degree=64, max_substeps=2)
+    assert e.value.code == B.ENOCONV
+    assert B.magnus_leja_plan(0.0, 1e-10)[0] == 1
+
+
+def test_quadrature_nodes():
+    t = B.magnus_quadrature_nodes(B.CF4, 0.25, 0.01, 3)
+    c1, c2 = 0.5 - math.sqrt(3) / 6, 0.5 + math.sqrt(3) / 6
+    for n in range(3):
+        assert abs(t[n, 0] - (0.25 + n * 0.01 + c1 * 0.01)) < 1e-16
+        assert abs(t[n, 1] - (0.25 + n * 0.01 + c2 * 0.01)) < 1e-16
+
+
+def test_null_context_errors_on_host():
+    L = B.lib()
+    h = B.Hamiltonian()
+    o = B.leja_opts()
+    assert L.expmv_leja(None, B.C.byref(h), 1.0, 0.0, 0.0, 0.1, None, None, 1, B.C.byref(o), None, None) == B.EINVAL
+    assert L.magnus_step_cf4(None, None, 0.1, 0.0, 0.0, None, None, 1, None, None, None) == B.EINVAL
+    assert L.propagate(None, None, 7, 0.1, 1, None, 1, None, 1, None, 1, None, None, None) == B.EINVAL
+    assert b"unknown method" in L.magnus_last_error()
+    assert L.magnus_destroy(None) == B.OK
