@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--no-m4", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -71,6 +73,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 16, dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": True, "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                          "copies": 3}), flush=True)
+        return
 
     cfg = inputs.CONFIGS["chain_n20"]
     n, tau, cfg_steps = cfg["n"], cfg["tau"], cfg["nsteps"]

@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -64,6 +65,7 @@ struct magnus_ctx {
   std::set<std::tuple<const void*, const void*, const void*, int64_t, int64_t>> validated;
   std::mutex mu;
   // kernel timing: (kind, start, stop) per recorded launch, events reused from a pool
+  int csr_variant = 0;  // 0 auto, 1 nonzero-streaming, 2 row-per-lane (MAGNUS_CSR_VARIANT)
   bool timing = false;
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;
   std::vector<hipEvent_t> pool;
@@ -192,7 +194,15 @@ struct ExpOp {
   double a, b, kappa;
 };
 
-int rows_per_block(int64_t dim) { return dim >= 65536 ? 64 : 16; }
+int rows_per_block(magnus_ctx* ctx, int64_t dim) {
+  if (ctx->csr_variant == 1) return dim >= 65536 ? 64 : 16;
+  if (ctx->csr_variant == 2) return magnus::kRowLane;
+  if (ctx->csr_variant == 3) return -32;
+  if (ctx->csr_variant == 4) return -128;
+  if (ctx->csr_variant == 5) return magnus::kWaveTile + 8;
+  if (ctx->csr_variant == 6) return magnus::kWaveTile + 16;
+  return dim >= 65536 ? magnus::kRowLane : 16;
+}
 
 hipEvent_t next_event(magnus_ctx* ctx) {
   if (ctx->pool_used == ctx->pool.size()) {
@@ -248,16 +258,18 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
       return magnus::launch_dense2_iter(reinterpret_cast<const double2*>(h->H1.val),
                                         reinterpret_cast<const double2*>(h->H2.val), dim, h->H1.ld, a, s);
     }));
+    HIP_TRY(magnus::launch_leja_decide(a, magnus::dense2_grid(dim), s));
     return MAGNUS_OK;
   }
   CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
   CsrDev t2{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
-  const int rpb = rows_per_block(dim);
+  const int rpb = rows_per_block(ctx, dim);
   if (op.kappa == 0.0) {
     a.x1 = win;
     a.x2 = win;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA, s,
                   [&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }));
+    HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
     return MAGNUS_OK;
   }
   // commutator: pass 1 writes U = H1 w, V = H2 w; pass 2 applies H1 V and H2 U
@@ -274,6 +286,7 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
   a.x2 = U;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_COMM, s,
                 [&] { return magnus::launch_csr2_iter(magnus::kLejaComm, t1, t2, dim, a, rpb, s); }));
+  HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
   return MAGNUS_OK;
 }
 
@@ -395,6 +408,7 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   c->device = device;
   c->max_dim = max_dim;
   c->max_batch = max_batch;
+  if (const char* v = getenv("MAGNUS_CSR_VARIANT")) c->csr_variant = atoi(v);
   c->max_grid = max_dim / 8 + 2;  // the smallest row block of any iteration kernel is 8 rows
   c->scan_len = 2 * (max_dim / 4 + 2) + 3 * (max_dim / 256 + 2);
   hipError_t e = hipMalloc(&c->vecs, sizeof(double2) * (size_t)kNumVec * (size_t)max_dim);

@@ -7,11 +7,11 @@
 namespace magnus {
 
 // Per-state control block in device memory.  One Leja substep runs as a
-// sequence of iteration kernels; the last workgroup of each iteration reduces
-// the norm partials in a fixed order, evaluates the early-termination test and
-// writes the verdict here for the next iteration to read.
+// sequence of iteration kernels, each followed by a one-workgroup kernel that
+// reduces the norm partials in a fixed order, evaluates the early-termination
+// test and writes the verdict here for the next iteration to read.
 struct Slot {
-  unsigned int counter;   // workgroups of the current kernel that have finished
+  unsigned int counter;   // unused (kept zero)
   int stopped;            // 1: the current substep has terminated early
   int iters_sub;          // iterations done in the current substep
   int status;             // sticky: bit 0 = non-finite norm seen
@@ -56,6 +56,14 @@ struct IterArgs {
   int check_stop;       // return at once if the substep has stopped
 };
 
+// Row-block selector of launch_csr2_iter: 16 or 64 rows per workgroup with
+// the nonzero-streaming kernel, or -32, -64, -128 for the row-per-lane kernel
+// with that many rows per workgroup.
+constexpr int kRowLane = -64;
+// kWaveTile + R selects the wave-tile kernel with R rows per wave (R = 8, 16;
+// four waves per workgroup).
+constexpr int kWaveTile = 1000;
+
 // Launch one iteration over `dim` rows of the two CSR terms.
 hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int dim,
                             const IterArgs& a, int rows_per_block, hipStream_t s);
@@ -78,6 +86,10 @@ int dense_gershgorin_grid(int dim);
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s);
 int dense2_grid(int dim);
+
+// Reduce the norm partials of the iteration launched just before (grid
+// workgroups) and write the early-termination verdict into the slot.
+hipError_t launch_leja_decide(const IterArgs& a, int grid, hipStream_t s);
 
 // Small helpers.
 hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_t s);

@@ -4,9 +4,10 @@
 // w <- A w - xi_{i-1} w, p <- p + d_i w), fused into a single pass over the
 // Hamiltonian: the matrix-vector product of both terms of H(t) = H1 + f H2
 // (Section 4), the shift, the accumulation into p, and the partial sums of
-// |w_i|^2 (and |v|^2 on the first iteration) for the error control.  The last
-// workgroup to finish reduces the partials in a fixed order and writes the
-// early-termination verdict for the next iteration, so the host never waits.
+// |w_i|^2 (and |v|^2 on the first iteration) for the error control.  A
+// one-workgroup kernel that follows reduces the partials in a fixed order and
+// writes the early-termination verdict for the next iteration to read, so the
+// host never waits.
 #include "kernels.h"
 
 #include <cmath>
@@ -60,10 +61,11 @@ __device__ __forceinline__ void leja_row(const IterArgs& a, int r, d2 y, double&
   pw += nrm2(wn);
 }
 
-// Block reduction of the norm partials, then the last-workgroup decision.
-__device__ void finish_iteration(const IterArgs& a, double pw, double pv) {
+// Block sums of the norm partials, one pair per workgroup (plain stores: the
+// reduction across workgroups happens in leja_decide_kernel, after this
+// kernel has finished, so no device-scope atomics or fences are needed).
+__device__ void block_partials(const IterArgs& a, double pw, double pv) {
   __shared__ double red[2][kThreads / 64];
-  __shared__ int amlast;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   pw = wave_sum(pw);
   pv = wave_sum(pv);
@@ -74,26 +76,39 @@ __device__ void finish_iteration(const IterArgs& a, double pw, double pv) {
     for (int w = 0; w < kThreads / 64; ++w) { bw += red[0][w]; bv += red[1][w]; }
     a.partials[2 * blockIdx.x] = bw;
     a.partials[2 * blockIdx.x + 1] = bv;
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.slot->counter, 1u);
-    amlast = (prev == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!amlast) return;
-  __threadfence();
+}
+
+// One workgroup: reduce the partials of the iteration just finished in a
+// fixed order, then the early-termination test of Section 3 (our reading:
+// stop once |d_i w_i| + |d_{i-1} w_{i-1}| <= tol |v|).  Every thread issues
+// all of its loads before summing, so the kernel costs about one memory
+// round trip.
+constexpr int kDecideThreads = 1024;
+constexpr int kDecidePer = 16;
+__global__ __launch_bounds__(kDecideThreads) void leja_decide_kernel(IterArgs a, int grid) {
+  __shared__ double red[2][kDecideThreads / 64];
+  if (a.check_stop && load_stopped(a.slot)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const d2* P = reinterpret_cast<const d2*>(a.partials);
   double sw = 0.0, sv = 0.0;
-  for (int k = tid; k < (int)gridDim.x; k += kThreads) {
-    sw += __hip_atomic_load(&a.partials[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    sv += __hip_atomic_load(&a.partials[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int k0 = 0; k0 < grid; k0 += kDecideThreads * kDecidePer) {
+    d2 v[kDecidePer];
+#pragma unroll
+    for (int u = 0; u < kDecidePer; ++u) {
+      const int k = k0 + u * kDecideThreads + tid;
+      v[u] = k < grid ? P[k] : d2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < kDecidePer; ++u) { sw += v[u].x; sv += v[u].y; }
   }
   sw = wave_sum(sw);
   sv = wave_sum(sv);
-  __syncthreads();
   if (lane == 0) { red[0][wv] = sw; red[1][wv] = sv; }
   __syncthreads();
   if (tid == 0) {
     double tw = 0.0, tv = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) { tw += red[0][w]; tv += red[1][w]; }
+    for (int w = 0; w < kDecideThreads / 64; ++w) { tw += red[0][w]; tv += red[1][w]; }
     Slot* S = a.slot;
     const double wn = sqrt(tw);
     const double vn = a.first ? sqrt(tv) : S->vnorm;
@@ -108,8 +123,6 @@ __device__ void finish_iteration(const IterArgs& a, double pw, double pv) {
     S->iters_sub = a.first ? 1 : S->iters_sub + 1;
     S->stopped = (bad || (a.early && est <= a.tol * vn)) ? 1 : 0;
     S->iters_total += 1;
-    __threadfence();
-    S->counter = 0u;
   }
 }
 
@@ -134,8 +147,10 @@ __global__ __launch_bounds__(kThreads) void csr2_iter_kernel(CsrDev t1, CsrDev t
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = L * ROWS;
   const int nrows = min(ROWS, dim - row0);
-  if (tid <= nrows) rps[0][tid] = t1.rp[row0 + tid];
-  if (tid >= 128 && tid - 128 <= nrows) rps[1][tid - 128] = t2.rp[row0 + tid - 128];
+  for (int i = tid; i <= nrows; i += kThreads) {
+    rps[0][i] = t1.rp[row0 + i];
+    rps[1][i] = t2.rp[row0 + i];
+  }
   __syncthreads();
   const int base1 = rps[0][0], n1 = rps[0][nrows] - base1;
   const int base2 = rps[1][0], n2 = rps[1][nrows] - base2;
@@ -222,7 +237,303 @@ __global__ __launch_bounds__(kThreads) void csr2_iter_kernel(CsrDev t1, CsrDev t
       }
       leja_row(a, r, y, pw, pv);
     }
-    finish_iteration(a, pw, pv);
+    block_partials(a, pw, pv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-term CSR iteration, row-per-lane variant.  The workgroup first copies
+// its rows' column indices and values (both terms) into LDS with coalesced,
+// non-temporal loads; then lane l of every wave owns row row0 + l and wave q
+// walks the row's entries k = q, q + 4, ... .  Neighbouring lanes therefore
+// gather x at the same position of neighbouring rows, which for structured
+// Hamiltonians (neighbouring basis states couple to neighbouring states) turns
+// most gathers into contiguous 1 KiB loads.  The four partial sums per row are
+// combined in LDS in a fixed order and wave 0 applies the Leja update to 64
+// consecutive rows with coalesced stores.
+// ---------------------------------------------------------------------------
+template <int ROWS, int MODE>
+__global__ __launch_bounds__(kThreads) void csr2_rowlane_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+  constexpr int NW = kThreads / ROWS;  // entry groups per row
+  constexpr int CAP = ROWS * 32;
+  constexpr int U = CAP / kThreads;
+  __shared__ d2 sval[CAP];
+  __shared__ int scol[CAP];
+  __shared__ int rps[2][ROWS + 1];
+  __shared__ d2 part[2][NW][ROWS];
+  __shared__ double wred[2][kThreads / 64];
+  if (a.check_stop && load_stopped(a.slot)) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid % ROWS, wv = tid / ROWS;  // row within the block, entry group
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int row0 = L * ROWS;
+  const int nrows = min(ROWS, dim - row0);
+  for (int i = tid; i <= nrows; i += kThreads) {
+    rps[0][i] = t1.rp[row0 + i];
+    rps[1][i] = t2.rp[row0 + i];
+  }
+  __syncthreads();
+  const int base1 = rps[0][0], n1 = rps[0][nrows] - base1;
+  const int base2 = rps[1][0], n2 = rps[1][nrows] - base2;
+  const int total = n1 + n2;
+  // this lane's row segments in the concatenated (term 1, term 2) sequence
+  int s1 = 0, e1 = 0, s2 = 0, e2 = 0;
+  if (lane < nrows) {
+    s1 = rps[0][lane] - base1;
+    e1 = rps[0][lane + 1] - base1;
+    s2 = n1 + rps[1][lane] - base2;
+    e2 = n1 + rps[1][lane + 1] - base2;
+  }
+  const d2* x1 = reinterpret_cast<const d2*>(a.x1);
+  const d2* x2 = reinterpret_cast<const d2*>(a.x2);
+  const d2* v1 = reinterpret_cast<const d2*>(t1.val);
+  const d2* v2 = reinterpret_cast<const d2*>(t2.val);
+  d2 acc1 = {0.0, 0.0}, acc2 = {0.0, 0.0};
+
+  for (int c0 = 0; c0 < total; c0 += CAP) {
+    const int cn = min(CAP, total - c0);
+    int col[U];
+    d2 val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = u * kThreads + tid;
+      const int g = c0 + k;
+      col[u] = 0;
+      val[u] = d2{0.0, 0.0};
+      if (k < cn) {
+        if (g < n1) {
+          col[u] = __builtin_nontemporal_load(t1.ci + base1 + g);
+          val[u] = __builtin_nontemporal_load(v1 + base1 + g);
+        } else {
+          col[u] = __builtin_nontemporal_load(t2.ci + base2 + (g - n1));
+          val[u] = __builtin_nontemporal_load(v2 + base2 + (g - n1));
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = u * kThreads + tid;
+      if (k < cn) {
+        scol[k] = col[u];
+        sval[k] = val[u];
+      }
+    }
+    __syncthreads();
+    const int hi = c0 + cn;
+    {
+      const int lo = max(s1, c0) + wv, end = min(e1, hi);
+#pragma unroll 4
+      for (int k = lo; k < end; k += NW) acc1 += cmul(sval[k - c0], x1[scol[k - c0]]);
+    }
+    {
+      const int lo = max(s2, c0) + wv, end = min(e2, hi);
+#pragma unroll 4
+      for (int k = lo; k < end; k += NW) acc2 += cmul(sval[k - c0], x2[scol[k - c0]]);
+    }
+    __syncthreads();
+  }
+  part[0][wv][lane] = acc1;
+  part[1][wv][lane] = acc2;
+  __syncthreads();
+  // threads 0..ROWS-1 finish one row each (lane == tid there)
+  const bool owner = tid < ROWS && lane < nrows;
+  const int r = row0 + lane;
+  d2 r1 = {0.0, 0.0}, r2 = {0.0, 0.0};
+  if (tid < ROWS) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      r1 += part[0][w][lane];
+      r2 += part[1][w][lane];
+    }
+  }
+  if constexpr (MODE == kSplit) {
+    if (owner) {
+      a.wout[r] = fromd2(r1);
+      a.pacc[r] = fromd2(r2);
+    }
+  } else {
+    double pw = 0.0, pv = 0.0;
+    if (owner) {
+      d2 y;
+      if constexpr (MODE == kLeja) {
+        y = rmul(a.a1, r1) + rmul(a.a2, r2);
+      } else {
+        const d2 Ur = x2[r], Vr = x1[r];
+        const d2 dl = r1 - r2;
+        y = rmul(a.a1, Ur) + rmul(a.a2, Vr) + d2{-a.kap * dl.y, a.kap * dl.x};
+      }
+      leja_row(a, r, y, pw, pv);
+    }
+    pw = wave_sum(pw);
+    pv = wave_sum(pv);
+    if ((tid & 63) == 0) { wred[0][tid >> 6] = pw; wred[1][tid >> 6] = pv; }
+    __syncthreads();
+    if (tid == 0) {
+      double bw = 0.0, bv = 0.0;
+      for (int k = 0; k < kThreads / 64; ++k) { bw += wred[0][k]; bv += wred[1][k]; }
+      a.partials[2 * blockIdx.x] = bw;
+      a.partials[2 * blockIdx.x + 1] = bv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-term CSR iteration, wave-tile variant.  Every wave owns RPW consecutive
+// rows and works through them on its own: it stages its rows' column indices
+// and values (both terms) in a private LDS slice with coalesced non-temporal
+// loads, gathers x with lanes laid out row-fastest (lane = g * RPW + r, so
+// neighbouring lanes gather the same entry position of neighbouring rows),
+// sums each row's G = 64 / RPW groups with shuffles in a fixed order and
+// applies the Leja update to its RPW rows.  No block-wide barrier separates
+// the phases, so the waves of a CU overlap freely; the only barrier combines
+// the four waves' norm partials at the end.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS accesses are done
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int RPW, int MODE>
+__global__ __launch_bounds__(kThreads) void csr2_wave_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+  constexpr int NWAVE = kThreads / 64;
+  constexpr int G = 64 / RPW;      // entry groups per row
+  constexpr int CAPW = RPW * 32;   // entries staged per chunk
+  constexpr int U = CAPW / 64;     // entries per lane per chunk
+  static_assert(RPW + 1 <= 32, "row pointers are loaded by half-waves");
+  __shared__ d2 sval[NWAVE][CAPW];
+  __shared__ int scol[NWAVE][CAPW];
+  __shared__ int srp[NWAVE][2][RPW + 1];
+  __shared__ double wred[2][NWAVE];
+  if (a.check_stop && load_stopped(a.slot)) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int row0 = (L * NWAVE + wv) * RPW;
+  const int nrows = max(0, min(RPW, dim - row0));
+  const int r = lane % RPW, g = lane / RPW;
+  const bool owner = (lane < RPW) && (r < nrows);
+  const int row = row0 + r;
+  double pw = 0.0, pv = 0.0;
+
+  if (nrows > 0) {
+    if (lane <= nrows) srp[wv][0][lane] = t1.rp[row0 + lane];
+    if (lane >= 32 && lane - 32 <= nrows) srp[wv][1][lane - 32] = t2.rp[row0 + lane - 32];
+    // own-row operands of the update, fetched early
+    d2 w_old = {0.0, 0.0}, p_old = {0.0, 0.0}, own1 = {0.0, 0.0}, own2 = {0.0, 0.0};
+    if (owner) {
+      if constexpr (MODE != kSplit) {
+        w_old = tod2(a.wcur[row]);
+        if (!a.first) p_old = tod2(a.pacc[row]);
+      }
+      if constexpr (MODE == kLejaComm) {
+        own1 = tod2(a.x1[row]);
+        own2 = tod2(a.x2[row]);
+      }
+    }
+    wave_lds_sync();
+    const int base1 = srp[wv][0][0], n1 = srp[wv][0][nrows] - base1;
+    const int base2 = srp[wv][1][0], n2 = srp[wv][1][nrows] - base2;
+    const int total = n1 + n2;
+    int s1 = 0, e1 = 0, s2 = 0, e2 = 0;
+    if (r < nrows) {
+      s1 = srp[wv][0][r] - base1;
+      e1 = srp[wv][0][r + 1] - base1;
+      s2 = n1 + srp[wv][1][r] - base2;
+      e2 = n1 + srp[wv][1][r + 1] - base2;
+    }
+    const d2* x1 = reinterpret_cast<const d2*>(a.x1);
+    const d2* x2 = reinterpret_cast<const d2*>(a.x2);
+    const d2* v1 = reinterpret_cast<const d2*>(t1.val);
+    const d2* v2 = reinterpret_cast<const d2*>(t2.val);
+    d2 acc1 = {0.0, 0.0}, acc2 = {0.0, 0.0};
+    for (int c0 = 0; c0 < total; c0 += CAPW) {
+      const int cn = min(CAPW, total - c0);
+      int col[U];
+      d2 val[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = u * 64 + lane;
+        const int gk = c0 + k;
+        col[u] = 0;
+        val[u] = d2{0.0, 0.0};
+        if (k < cn) {
+          if (gk < n1) {
+            col[u] = __builtin_nontemporal_load(t1.ci + base1 + gk);
+            val[u] = __builtin_nontemporal_load(v1 + base1 + gk);
+          } else {
+            col[u] = __builtin_nontemporal_load(t2.ci + base2 + (gk - n1));
+            val[u] = __builtin_nontemporal_load(v2 + base2 + (gk - n1));
+          }
+        }
+      }
+      wave_lds_sync();  // the previous chunk's LDS reads are done
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = u * 64 + lane;
+        if (k < cn) {
+          scol[wv][k] = col[u];
+          sval[wv][k] = val[u];
+        }
+      }
+      wave_lds_sync();
+      const int hi = c0 + cn;
+      {
+        const int lo = max(s1, c0) + g, end = min(e1, hi);
+#pragma unroll 4
+        for (int k = lo; k < end; k += G) acc1 += cmul(sval[wv][k - c0], x1[scol[wv][k - c0]]);
+      }
+      {
+        const int lo = max(s2, c0) + g, end = min(e2, hi);
+#pragma unroll 4
+        for (int k = lo; k < end; k += G) acc2 += cmul(sval[wv][k - c0], x2[scol[wv][k - c0]]);
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= RPW; off >>= 1) {
+      acc1.x += __shfl_xor(acc1.x, off, 64);
+      acc1.y += __shfl_xor(acc1.y, off, 64);
+      acc2.x += __shfl_xor(acc2.x, off, 64);
+      acc2.y += __shfl_xor(acc2.y, off, 64);
+    }
+    if (owner) {
+      if constexpr (MODE == kSplit) {
+        a.wout[row] = fromd2(acc1);
+        a.pacc[row] = fromd2(acc2);
+      } else {
+        d2 y;
+        if constexpr (MODE == kLeja) {
+          y = rmul(a.a1, acc1) + rmul(a.a2, acc2);
+        } else {
+          // own2 = U_r (term-2 gather vector), own1 = V_r (term-1 gather vector)
+          const d2 dl = acc1 - acc2;
+          y = rmul(a.a1, own2) + rmul(a.a2, own1) + d2{-a.kap * dl.y, a.kap * dl.x};
+        }
+        const d2 wn = y - rmul(a.sigma, w_old);
+        d2 p;
+        if (a.first) {
+          p = cmul(tod2(a.d0), w_old) + cmul(tod2(a.d), wn);
+          pv = nrm2(w_old);
+        } else {
+          p = p_old + cmul(tod2(a.d), wn);
+        }
+        a.wout[row] = fromd2(wn);
+        a.pacc[row] = fromd2(p);
+        pw = nrm2(wn);
+      }
+    }
+  }
+  if constexpr (MODE != kSplit) {
+    pw = wave_sum(pw);
+    pv = wave_sum(pv);
+    if (lane == 0) { wred[0][wv] = pw; wred[1][wv] = pv; }
+    __syncthreads();
+    if (tid == 0) {
+      double bw = 0.0, bv = 0.0;
+      for (int k = 0; k < NWAVE; ++k) { bw += wred[0][k]; bv += wred[1][k]; }
+      a.partials[2 * blockIdx.x] = bw;
+      a.partials[2 * blockIdx.x + 1] = bv;
+    }
   }
 }
 
@@ -275,7 +586,7 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
       leja_row(a, rbase + r, y, pw, pv);
     }
   }
-  finish_iteration(a, pw, pv);
+  block_partials(a, pw, pv);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,7 +685,11 @@ __global__ void slot_reset_kernel(Slot* s, int n) {
 
 }  // namespace
 
-int csr2_grid(int dim, int rows_per_block) { return (dim + rows_per_block - 1) / rows_per_block; }
+int csr2_grid(int dim, int rows_per_block) {
+  int rows = rows_per_block < 0 ? -rows_per_block : rows_per_block;
+  if (rows_per_block > kWaveTile) rows = (rows_per_block - kWaveTile) * (kThreads / 64);
+  return (dim + rows - 1) / rows;
+}
 
 hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a,
                             int rows_per_block, hipStream_t s) {
@@ -388,6 +703,29 @@ hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int di
   MAGNUS_CSR_CASE(16, kSplit)
   MAGNUS_CSR_CASE(16, kLejaComm)
 #undef MAGNUS_CSR_CASE
+#define MAGNUS_ROWLANE_CASE(R)                                                                     \
+  if (rows_per_block == -R) {                                                                      \
+    const int g = csr2_grid(dim, -R);                                                              \
+    if (mode == kLeja) csr2_rowlane_kernel<R, kLeja><<<g, kThreads, 0, s>>>(t1, t2, dim, a);       \
+    else if (mode == kSplit) csr2_rowlane_kernel<R, kSplit><<<g, kThreads, 0, s>>>(t1, t2, dim, a); \
+    else csr2_rowlane_kernel<R, kLejaComm><<<g, kThreads, 0, s>>>(t1, t2, dim, a);                 \
+    return hipGetLastError();                                                                      \
+  }
+  MAGNUS_ROWLANE_CASE(32)
+  MAGNUS_ROWLANE_CASE(64)
+  MAGNUS_ROWLANE_CASE(128)
+#undef MAGNUS_ROWLANE_CASE
+#define MAGNUS_WAVE_CASE(R)                                                                         \
+  if (rows_per_block == kWaveTile + R) {                                                            \
+    const int g = csr2_grid(dim, rows_per_block);                                                   \
+    if (mode == kLeja) csr2_wave_kernel<R, kLeja><<<g, kThreads, 0, s>>>(t1, t2, dim, a);           \
+    else if (mode == kSplit) csr2_wave_kernel<R, kSplit><<<g, kThreads, 0, s>>>(t1, t2, dim, a);    \
+    else csr2_wave_kernel<R, kLejaComm><<<g, kThreads, 0, s>>>(t1, t2, dim, a);                     \
+    return hipGetLastError();                                                                       \
+  }
+  MAGNUS_WAVE_CASE(8)
+  MAGNUS_WAVE_CASE(16)
+#undef MAGNUS_WAVE_CASE
   return hipErrorInvalidValue;
 }
 
@@ -422,6 +760,11 @@ hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_
   if (n <= 0) return hipSuccess;
   const long long grid = (n + kThreads - 1) / kThreads;
   copy_kernel<<<(unsigned)grid, kThreads, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_leja_decide(const IterArgs& a, int grid, hipStream_t s) {
+  leja_decide_kernel<<<1, kDecideThreads, 0, s>>>(a, grid);
   return hipGetLastError();
 }
 
