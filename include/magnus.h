@@ -138,6 +138,14 @@ typedef struct {
  * EHIP (device or allocation failure). */
 int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t device);
 
+/* Reserve (once) a dim x dim complex128 device buffer in the context for the
+ * assembled exponent H_hat = a H1 + b H2 of dense terms.  With it, groups of
+ * states that share the field run one MFMA GEMM per Leja iteration instead of
+ * two (Section 4 assembles H(t) on the device likewise).  An explicit
+ * allocation entry point: calls made without it work, at twice the flops.
+ * Errors: EINVAL (dim < 1), EHIP (allocation failure). */
+int magnus_reserve_dense(magnus_ctx* ctx, int64_t dim);
+
 /* Free the workspace and the context (NULL is accepted). */
 int magnus_destroy(magnus_ctx* ctx);
 
@@ -203,6 +211,38 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
               void* checkpoints, int32_t every_k, const magnus_leja_opts* opts,
               magnus_stats* stats, magnus_stream stream);
 
+/* ---- adjoint (gradient of a final-state fidelity) ------------------------------ */
+
+/* Bytes of device workspace magnus_propagate_adjoint needs (or -1 for bad
+ * arguments): checkpoints every every_k steps, one segment of recomputed
+ * states, and a few vectors. */
+int64_t magnus_adjoint_workspace_bytes(int64_t dim, int64_t nsteps, int32_t every_k);
+
+/* Loss L = 1 - |psi_target^H psi_N|^2 of an nsteps-step Cf4 propagation from
+ * psi0 (Method Cf4, Section 2; t_n = n tau with the caller's field samples)
+ * and its gradient with respect to P control parameters, by a backward sweep:
+ * lambda_N = psi_target, lambda_n = E(n)^H lambda_{n+1} (exponentials with
+ * -tau), and for each step the two scalars lambda^H L(A, E) phi, where the
+ * Frechet derivative L of the matrix exponential at A = -i tau H_hat in the
+ * direction E = -i tau H2 is the upper-right block of the exponential of the
+ * block matrix [[A, E], [0, A]] (Leja recurrence on 2-vectors).
+ *   f_nodes   HOST double[nsteps][2]: f(t_n + c_1 tau), f(t_n + c_2 tau).
+ *   df_nodes  HOST double[nsteps][2][P]: derivatives of those samples with respect
+ *             to each parameter.
+ *   psi0, psi_target  DEVICE, dim complex128 each (not modified).
+ *   every_k   checkpoint spacing: states are stored every every_k steps and each
+ *             segment is recomputed during the backward sweep.
+ *   workspace DEVICE scratch of at least magnus_adjoint_workspace_bytes bytes,
+ *             caller-owned.
+ *   loss      HOST double; grad HOST double[P].
+ * H1, H2 must be CSR and the context needs max_batch >= 2.  Synchronous.
+ * Errors: EINVAL, EDOMAIN, ENOMEM (workspace or context too small), ENOCONV, EHIP, ENAN. */
+int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, int64_t nsteps,
+                             const double* f_nodes, const double* df_nodes, int32_t nparams, const void* psi0,
+                             const void* psi_target, int32_t every_k, void* workspace, int64_t workspace_bytes,
+                             double* loss, double* grad, const magnus_leja_opts* opts, magnus_stats* stats,
+                             magnus_stream stream);
+
 /* ---- kernel timing (profiling aid) ---------------------------------------------- */
 
 /* Kernel classes timed by magnus_timing. */
@@ -210,6 +250,8 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
 #define MAGNUS_KERNEL_CSR_SPLIT  1  /* first pass of a commutator iteration */
 #define MAGNUS_KERNEL_CSR_COMM   2  /* second pass of a commutator iteration */
 #define MAGNUS_KERNEL_DENSE_LEJA 3  /* two-term dense Leja iteration */
+#define MAGNUS_KERNEL_CSR_MULTI  4  /* two-term CSR Leja iteration on a group of states */
+#define MAGNUS_KERNEL_DENSE_MFMA 5  /* dense group Leja iteration (FP64 MFMA GEMM) */
 
 /* enable = 1: from now on bracket every iteration kernel the context launches
  * with a pair of HIP events on the call's stream (previous records are

@@ -59,8 +59,9 @@ _lib = None
 EXPORTS = ("magnus_create", "magnus_destroy", "magnus_last_error", "magnus_check", "magnus_spectral_bounds",
            "expmv_leja", "magnus_step_cf4", "magnus_step_m4", "propagate", "magnus_quadrature_nodes",
            "magnus_leja_points", "magnus_divided_differences", "magnus_leja_error", "magnus_leja_plan",
-           "magnus_timing", "magnus_timing_read")
-KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA = 0, 1, 2, 3
+           "magnus_timing", "magnus_timing_read", "magnus_reserve_dense", "magnus_adjoint_workspace_bytes",
+           "magnus_propagate_adjoint")
+KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA, KERNEL_CSR_MULTI, KERNEL_DENSE_MFMA = 0, 1, 2, 3, 4, 5
 
 
 def lib():
@@ -91,6 +92,10 @@ def lib():
         "magnus_leja_plan": (C.c_int, [dbl, dbl, i32, i32, P(i32), P(i32), P(dbl)]),
         "magnus_timing": (C.c_int, [vp, i32]),
         "magnus_timing_read": (C.c_int, [vp, i32, P(dbl), P(i64)]),
+        "magnus_reserve_dense": (C.c_int, [vp, i64]),
+        "magnus_adjoint_workspace_bytes": (i64, [i64, i64, i32]),
+        "magnus_propagate_adjoint": (C.c_int, [vp, P(Hamiltonian), dbl, i64, P(dbl), P(dbl), i32, vp, vp, i32, vp,
+                                               i64, P(dbl), P(dbl), P(LejaOpts), P(Stats), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -181,6 +186,10 @@ class Context:
 
     def check(self):
         _check(lib().magnus_check(self.handle, _stream()))
+
+    def reserve_dense(self, dim: int):
+        """Let groups of states on dense terms use one assembled exponent per Leja iteration."""
+        _check(lib().magnus_reserve_dense(self.handle, dim))
 
     def timing(self, enable: bool):
         _check(lib().magnus_timing(self.handle, int(bool(enable))))
@@ -321,3 +330,38 @@ def propagate(ctx: Context, ham: DeviceHamiltonian, method: int, tau: float, f_n
                          batch, ck, every_k, C.byref(o), C.byref(st) if stats else None, _stream())
     s = _finish(rc, st, stats)
     return (psi, s) if stats else psi
+
+
+def magnus_adjoint_workspace_bytes(dim: int, nsteps: int, every_k: int) -> int:
+    return int(lib().magnus_adjoint_workspace_bytes(dim, nsteps, every_k))
+
+
+def magnus_propagate_adjoint(ctx: Context, ham: DeviceHamiltonian, tau: float, f_nodes, df_nodes, psi0, psi_target,
+                             every_k: int = 16, opts: LejaOpts | None = None, stats: bool = False, workspace=None):
+    """Loss 1 - |<psi_target, psi_N>|^2 of a Cf4 run and its gradient with respect to the
+    parameters behind the field samples.  f_nodes (nsteps, 2); df_nodes (nsteps, 2, P).
+    Returns (loss, grad[P]) (and stats when asked)."""
+    torch = _torch()
+    f = np.ascontiguousarray(f_nodes, dtype=np.float64)
+    df = np.ascontiguousarray(df_nodes, dtype=np.float64)
+    nsteps = f.shape[0]
+    if f.shape != (nsteps, 2) or df.ndim != 3 or df.shape[:2] != (nsteps, 2):
+        raise ValueError("f_nodes must be (nsteps, 2) and df_nodes (nsteps, 2, P)")
+    P = df.shape[2]
+    for t in (psi0, psi_target):
+        if _states(t, ham.dim) != 1:
+            raise ValueError("psi0 and psi_target are single states")
+    need = magnus_adjoint_workspace_bytes(ham.dim, nsteps, every_k)
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=psi0.device)
+    loss = C.c_double()
+    grad = np.zeros(max(P, 1))
+    st = Stats()
+    o = opts or leja_opts()
+    rc = lib().magnus_propagate_adjoint(ctx.handle, C.byref(ham.struct), tau, nsteps, _dptr(f), _dptr(df), P,
+                                        _ptr(psi0), _ptr(psi_target), every_k, _ptr(workspace),
+                                        workspace.numel() * workspace.element_size(), C.byref(loss), _dptr(grad),
+                                        C.byref(o), C.byref(st) if stats else None, _stream())
+    s = _finish(rc, st, stats)
+    out = (loss.value, grad[:P].copy())
+    return (out + (s,)) if stats else out

@@ -22,9 +22,11 @@
 #include "kernels.h"
 #include "planner.h"
 
+using magnus::ColParam;
 using magnus::CsrDev;
 using magnus::ExpPlan;
 using magnus::IterArgs;
+using magnus::MultiArgs;
 using magnus::Slot;
 
 namespace {
@@ -48,7 +50,10 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 // Workspace vectors per state.
-enum Vec { kA = 0, kB, kS0, kS1, kS2, kU, kV, kNumVec };
+enum Vec { kA = 0, kB, kS0, kS1, kS2, kU, kV, kY, kNumVec };
+
+// Device table of per-state Leja parameters (ColParam entries) filled once per call segment.
+constexpr size_t kTableCap = 1 << 18;
 
 }  // namespace
 
@@ -56,9 +61,14 @@ struct magnus_ctx {
   int device = 0;
   int64_t max_dim = 0;
   int32_t max_batch = 0;
-  double2* vecs = nullptr;     // kNumVec * max_dim (states are processed in turn)
-  Slot* slots = nullptr;       // one control block
-  double* partials = nullptr;  // 2 * max_grid
+  double2* vecs = nullptr;     // kNumVec vectors of max_dim * max_batch entries
+  Slot* slots = nullptr;       // one control block per state of a batch
+  int nslots = 0;
+  ColParam* table = nullptr;   // kTableCap entries
+  double2* assembled = nullptr;  // magnus_reserve_dense
+  int64_t assembled_dim = 0;
+  double* partials = nullptr;  // npartials doubles
+  size_t npartials = 0;
   int64_t max_grid = 0;
   double* scan = nullptr;      // per-workgroup outputs of the Gershgorin scans
   int64_t scan_len = 0;
@@ -71,7 +81,7 @@ struct magnus_ctx {
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
 
-  double2* vec(int k) { return vecs + (size_t)k * (size_t)max_dim; }
+  double2* vec(int k) { return vecs + (size_t)k * (size_t)max_dim * (size_t)max_batch; }
 };
 
 namespace {
@@ -335,25 +345,40 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
 
 int begin_call(magnus_ctx* ctx, hipStream_t s) {
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(magnus::launch_slot_reset(ctx->slots, 1, s));
+  HIP_TRY(magnus::launch_slot_reset(ctx->slots, ctx->nslots, s));
+  return MAGNUS_OK;
+}
+
+// Sum of the per-state counters and the union of the status bits.
+int read_slots(magnus_ctx* ctx, hipStream_t s, long long* iters, int* status) {
+  std::vector<Slot> hs(ctx->nslots);
+  HIP_TRY(hipMemcpyAsync(hs.data(), ctx->slots, sizeof(Slot) * hs.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *iters = 0;
+  *status = 0;
+  for (const Slot& x : hs) {
+    *iters += x.iters_total;
+    *status |= x.status;
+  }
   return MAGNUS_OK;
 }
 
 int end_call(magnus_ctx* ctx, const Acc& acc, double tol_e, magnus_stats* st, hipStream_t s) {
   if (!st) return MAGNUS_OK;
-  Slot hs;
-  HIP_TRY(hipMemcpyAsync(&hs, ctx->slots, sizeof(Slot), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  long long iters = 0;
+  int status = 0;
+  int rc = read_slots(ctx, s, &iters, &status);
+  if (rc) return rc;
   st->exponentials = acc.exponentials;
   st->substeps = acc.substeps;
   st->planned_iters = acc.planned;
-  st->iters = hs.iters_total;
-  st->hv_products = hs.iters_total * acc.products_per_iter;
+  st->iters = iters;
+  st->hv_products = iters * acc.products_per_iter;
   st->max_degree_used = acc.max_m;
   st->max_substeps_used = acc.max_s;
   st->max_err_bound = acc.max_bound;
   st->tol_per_exp = tol_e;
-  if (hs.status & 1) return fail(MAGNUS_ENAN, "non-finite vector norm met during the call");
+  if (status & 1) return fail(MAGNUS_ENAN, "non-finite vector norm met during the call");
   return MAGNUS_OK;
 }
 
@@ -381,6 +406,241 @@ int m4_state(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1
   const double fbar = 0.5 * (f1 + f2);
   const double kappa = magnus::kSqrt3 * tau * (f2 - f1) / 12.0;
   return run_exponential(ctx, ExpOp{h, 1.0, fbar, kappa}, tau, in, out, tol_e, o, acc, s);
+}
+
+// ---------------------------------------------------------------------------
+// Several states per iteration (interleaved workspace, one CSR pass for all).
+// ---------------------------------------------------------------------------
+
+// One exponential of a group of B states: exp(-i tau (a_b H1 + b_b H2)) for
+// state b.  All states share the substep count s and run max_b m_b
+// iterations; a state whose own degree m_b is smaller gets d_i = 0 beyond it.
+struct MultiExp {
+  int B = 0, s = 1, m = 1;
+  int dense_terms = 0;           // dense: 1 (assembled, with acoef/bcoef below) or 2
+  double ca = 0.0, cb = 0.0;     // coefficients of the assembled exponent
+  size_t table_off = 0;          // first ColParam of this exponential ([i-1][b])
+  double tau = 0.0;
+  int frechet = 0;               // block vector of [[H, H2], [0, H]] (B == 2)
+  const double2* src = nullptr;  // interleaved, dim * B
+  double2* dst = nullptr;
+};
+
+int plan_multi(const magnus_hamiltonian* h, const double* acoef, const double* bcoef, int B, double tau,
+               double tol_e, const magnus_leja_opts* o, int frechet, std::vector<ColParam>* table,
+               MultiExp* out, Acc* acc, bool assembled = false) {
+  std::vector<double> lo(B), hi(B);
+  int s = 1;
+  for (int b = 0; b < B; ++b) {
+    magnus::weyl_interval(acoef[b], h->H1.lam_min, h->H1.lam_max, bcoef[b], h->H2.lam_min, h->H2.lam_max, 0.0, 0.0,
+                          0.0, &lo[b], &hi[b]);
+    ExpPlan t;
+    if (!magnus::plan_exponential(tau, lo[b], hi[b], tol_e, o->max_degree, o->max_substeps, &t))
+      return fail(MAGNUS_ENOCONV, "no degree <= %d with <= %d substeps reaches tol %g", o->max_degree,
+                  o->max_substeps, tol_e);
+    s = std::max(s, t.lp.s);
+  }
+  std::vector<ExpPlan> P(B);
+  int m = 1;
+  double worst = 0.0;
+  for (int b = 0; b < B; ++b) {
+    const double coupling =
+        frechet ? std::fmax(std::fabs(h->H2.lam_min), std::fabs(h->H2.lam_max)) : 0.0;
+    if (!magnus::plan_exponential_fixed_s(tau, lo[b], hi[b], tol_e, s, o->max_degree, &P[b], coupling))
+      return fail(MAGNUS_ENOCONV, "no degree <= %d reaches tol %g with %d substeps", o->max_degree, tol_e, s);
+    m = std::max(m, P[b].lp.m);
+    worst = std::max(worst, P[b].lp.bound);
+  }
+  const auto& xi = magnus::leja_points();
+  out->B = B;
+  out->s = s;
+  out->m = m;
+  out->tau = tau;
+  out->frechet = frechet;
+  out->table_off = table->size();
+  for (int i = 1; i <= m; ++i)
+    for (int b = 0; b < B; ++b) {
+      const ExpPlan& p = P[b];
+      ColParam c{};
+      c.a1 = assembled ? p.scale : p.scale * acoef[b];
+      c.a2 = assembled ? 0.0 : p.scale * bcoef[b];
+      c.sigma = p.scale * p.c + xi[i - 1];
+      const std::complex<double> d = i <= p.lp.m ? p.d[i] : std::complex<double>(0.0, 0.0);
+      c.dre = d.real();
+      c.dim = d.imag();
+      c.dabs = std::abs(d);
+      c.d0re = p.d[0].real();
+      c.d0im = p.d[0].imag();
+      c.d0abs = std::abs(p.d[0]);
+      c.coup = frechet ? p.scale : 0.0;
+      table->push_back(c);
+    }
+  acc->exponentials += 1;
+  acc->substeps += s;
+  acc->planned += (int64_t)m * s * B;
+  acc->max_m = std::max(acc->max_m, m);
+  acc->max_s = std::max(acc->max_s, s);
+  acc->max_bound = std::max(acc->max_bound, worst);
+  return MAGNUS_OK;
+}
+
+int upload_table(magnus_ctx* ctx, const std::vector<ColParam>& table, hipStream_t s) {
+  if (table.empty()) return MAGNUS_OK;
+  if (table.size() > kTableCap) return fail(MAGNUS_ENOMEM, "parameter table of %zu entries exceeds %zu", table.size(), kTableCap);
+  HIP_TRY(hipMemcpyAsync(ctx->table, table.data(), sizeof(ColParam) * table.size(), hipMemcpyHostToDevice, s));
+  return MAGNUS_OK;
+}
+
+// Launch the iterations of one planned multi-state exponential.
+int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E, double tol_e, int early,
+                 hipStream_t s) {
+  const int dim = (int)h->H1.dim;
+  const int B = E.B;
+  const size_t n = (size_t)dim * B;
+  CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
+  CsrDev t2{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
+  const bool dense = h->H1.format == MAGNUS_DENSE;
+  const int grid = dense ? magnus::dense_mfma_row_blocks(dim) : magnus::csr2_multi_grid(dim, B);
+  const int mode = E.frechet ? magnus::kMultiFrechet : magnus::kMultiLeja;
+  const double2* D1 = reinterpret_cast<const double2*>(h->H1.val);
+  const double2* D2 = reinterpret_cast<const double2*>(h->H2.val);
+  long long ldd = h->H1.ld;
+  if (dense && E.dense_terms == 1) {
+    HIP_TRY(magnus::launch_dense_assemble(D1, D2, h->H1.ld, dim, E.ca, E.cb, ctx->assembled, s));
+    D1 = ctx->assembled;
+    ldd = dim;
+  }
+  const double tol_sub = tol_e / (2.0 * E.s);
+  const double2* cur = E.src;
+  for (int sub = 0; sub < E.s; ++sub) {
+    const bool last = (sub == E.s - 1);
+    double2* Pbuf;
+    if (last && E.dst != cur) Pbuf = E.dst;
+    else Pbuf = (cur == ctx->vec(kS0)) ? ctx->vec(kS1) : ctx->vec(kS0);
+    for (int i = 1; i <= E.m; ++i) {
+      MultiArgs a{};
+      a.x = (i == 1) ? cur : ((i - 1) % 2 == 1 ? ctx->vec(kA) : ctx->vec(kB));
+      a.wout = (i % 2 == 1) ? ctx->vec(kA) : ctx->vec(kB);
+      a.pacc = Pbuf;
+      a.slots = ctx->slots;
+      a.partials = ctx->partials;
+      a.prm = ctx->table + E.table_off + (size_t)(i - 1) * B;
+      a.B = B;
+      a.first = (i == 1);
+      a.check_stop = (i != 1);
+      a.early = early;
+      a.tol = tol_sub;
+      a.joint = E.frechet;
+      if (dense)
+        HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_MFMA, s,
+                      [&] { return magnus::launch_dense_mfma(E.dense_terms, D1, D2, ldd, dim, a, s); }));
+      else
+        HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_MULTI, s, [&] { return magnus::launch_csr2_multi(mode, t1, t2, dim, a, s); }));
+      HIP_TRY(magnus::launch_multi_decide(a, grid, s));
+    }
+    cur = Pbuf;
+  }
+  if (cur != E.dst) HIP_TRY(magnus::launch_copy(cur, E.dst, (long long)n, s));
+  return MAGNUS_OK;
+}
+
+// Largest supported group size for the remaining states.
+int group_size(int remaining) {
+  for (int g : {32, 16, 8, 4, 2})
+    if (remaining >= g) return g;
+  return 1;
+}
+
+bool multi_ok(const magnus_hamiltonian* h, double kappa) { return kappa == 0.0; }
+
+// Dense groups take every remaining state at once; CSR groups 32, 16, 8, 4, 2.
+int group_for(const magnus_hamiltonian* h, int remaining) {
+  return h->H1.format == MAGNUS_DENSE ? (remaining > 1 ? remaining : 1) : group_size(remaining);
+}
+
+// Plan one group exponential, assembling the dense exponent when all states share it.
+int plan_group(magnus_ctx* ctx, const magnus_hamiltonian* h, const double* acoef, const double* bcoef, int B,
+               double tau, double tol_e, const magnus_leja_opts* o, std::vector<ColParam>* table, MultiExp* E,
+               Acc* acc) {
+  bool shared = true;
+  for (int b = 1; b < B; ++b) shared = shared && acoef[b] == acoef[0] && bcoef[b] == bcoef[0];
+  const bool dense = h->H1.format == MAGNUS_DENSE;
+  const bool assemble = dense && shared && ctx->assembled && ctx->assembled_dim >= h->H1.dim;
+  int rc = plan_multi(h, acoef, bcoef, B, tau, tol_e, o, 0, table, E, acc, assemble);
+  if (rc) return rc;
+  E->dense_terms = dense ? (assemble ? 1 : 2) : 0;
+  E->ca = acoef[0];
+  E->cb = bcoef[0];
+  return MAGNUS_OK;
+}
+
+// dst[c] = exp(-i tau (a H1 + b_c H2)) src[c] for the states c0..c0+B-1
+// (b-major caller layout in and out).
+int multi_expmv_group(magnus_ctx* ctx, const magnus_hamiltonian* h, int B, const double* acoef,
+                      const double* bcoef, double tau, const double2* src, double2* dst, double tol_e,
+                      const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  const int dim = (int)h->H1.dim;
+  double2* Y = ctx->vec(kY);
+  HIP_TRY(magnus::launch_pack(src, Y, dim, B, s));
+  std::vector<ColParam> table;
+  MultiExp E;
+  int rc = plan_group(ctx, h, acoef, bcoef, B, tau, tol_e, o, &table, &E, acc);
+  if (rc) return rc;
+  if ((rc = upload_table(ctx, table, s))) return rc;
+  E.src = Y;
+  E.dst = Y;
+  if ((rc = launch_multi(ctx, h, E, tol_e, o->early_termination, s))) return rc;
+  HIP_TRY(magnus::launch_unpack(Y, dst, dim, B, s));
+  return MAGNUS_OK;
+}
+
+// Cf4 steps for a group of B states held interleaved in kY, f values per
+// state: fn(c, n, j) = f(t_n + c_j tau) of state c.
+template <class F>
+int multi_cf4_steps(magnus_ctx* ctx, const magnus_hamiltonian* h, int B, double tau, int64_t n0, int64_t n1,
+                    F fn, double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  double2* Y = ctx->vec(kY);
+  double2* M = ctx->vec(kS2);
+  std::vector<double> av(B, 0.5), bb(B), bg(B);
+  // steps are planned and uploaded in segments that fit the parameter table
+  int64_t n = n0;
+  while (n < n1) {
+    std::vector<ColParam> table;
+    std::vector<MultiExp> exps;
+    int64_t k = n;
+    for (; k < n1; ++k) {
+      for (int c = 0; c < B; ++c) {
+        const double f1 = fn(c, k, 0), f2 = fn(c, k, 1);
+        bb[c] = magnus::kAlpha2 * f1 + magnus::kAlpha1 * f2;
+        bg[c] = magnus::kAlpha1 * f1 + magnus::kAlpha2 * f2;
+      }
+      const size_t mark = table.size();
+      MultiExp Eb, Ea;
+      Acc trial = *acc;
+      int rc = plan_group(ctx, h, av.data(), bb.data(), B, tau, tol_e, o, &table, &Eb, &trial);
+      if (rc) return rc;
+      rc = plan_group(ctx, h, av.data(), bg.data(), B, tau, tol_e, o, &table, &Ea, &trial);
+      if (rc) return rc;
+      if (table.size() > kTableCap) {
+        if (k == n) return fail(MAGNUS_ENOMEM, "one step needs more than the parameter table holds");
+        table.resize(mark);
+        break;
+      }
+      *acc = trial;
+      Eb.src = Y;
+      Eb.dst = M;
+      Ea.src = M;
+      Ea.dst = Y;
+      exps.push_back(Eb);
+      exps.push_back(Ea);
+    }
+    int rc = upload_table(ctx, table, s);
+    if (rc) return rc;
+    for (const MultiExp& E : exps)
+      if ((rc = launch_multi(ctx, h, E, tol_e, o->early_termination, s))) return rc;
+    n = k;
+  }
+  return MAGNUS_OK;
 }
 
 int check_batch(magnus_ctx* ctx, int32_t batch) {
@@ -411,12 +671,16 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   if (const char* v = getenv("MAGNUS_CSR_VARIANT")) c->csr_variant = atoi(v);
   c->max_grid = max_dim / 8 + 2;  // the smallest row block of any iteration kernel is 8 rows
   c->scan_len = 2 * (max_dim / 4 + 2) + 3 * (max_dim / 256 + 2);
-  hipError_t e = hipMalloc(&c->vecs, sizeof(double2) * (size_t)kNumVec * (size_t)max_dim);
-  if (e == hipSuccess) e = hipMalloc(&c->slots, sizeof(Slot));
-  if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * 2 * (size_t)c->max_grid);
+  c->nslots = std::max<int>(2, max_batch);
+  const size_t nvec = (size_t)kNumVec * (size_t)max_dim * (size_t)max_batch;
+  hipError_t e = hipMalloc(&c->vecs, sizeof(double2) * nvec);
+  if (e == hipSuccess) e = hipMalloc(&c->slots, sizeof(Slot) * c->nslots);
+  if (e == hipSuccess) e = hipMalloc(&c->table, sizeof(ColParam) * kTableCap);
+  c->npartials = 2 * (size_t)c->max_grid + (size_t)max_dim * (size_t)std::max(1, max_batch) / 8 + (size_t)max_dim + 64;
+  if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->npartials);
   if (e == hipSuccess) e = hipMalloc(&c->scan, sizeof(double) * (size_t)c->scan_len);
-  if (e == hipSuccess) e = hipMemset(c->slots, 0, sizeof(Slot));
-  if (e == hipSuccess) e = hipMemset(c->vecs, 0, sizeof(double2) * (size_t)kNumVec * (size_t)max_dim);
+  if (e == hipSuccess) e = hipMemset(c->slots, 0, sizeof(Slot) * c->nslots);
+  if (e == hipSuccess) e = hipMemset(c->vecs, 0, sizeof(double2) * nvec);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     magnus_destroy(c);
@@ -427,11 +691,29 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   return MAGNUS_OK;
 }
 
+int magnus_reserve_dense(magnus_ctx* ctx, int64_t dim) {
+  if (!ctx) return fail(MAGNUS_EINVAL, "null context");
+  if (dim < 1 || dim > ctx->max_dim) return fail(MAGNUS_EINVAL, "dim %lld outside 1..max_dim", (long long)dim);
+  if (ctx->assembled_dim >= dim) return MAGNUS_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (ctx->assembled) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(ctx->assembled));
+    ctx->assembled = nullptr;
+    ctx->assembled_dim = 0;
+  }
+  HIP_TRY(hipMalloc(&ctx->assembled, sizeof(double2) * (size_t)dim * (size_t)dim));
+  ctx->assembled_dim = dim;
+  return MAGNUS_OK;
+}
+
 int magnus_destroy(magnus_ctx* ctx) {
   if (!ctx) return MAGNUS_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->vecs) (void)hipFree(ctx->vecs);
   if (ctx->slots) (void)hipFree(ctx->slots);
+  if (ctx->table) (void)hipFree(ctx->table);
+  if (ctx->assembled) (void)hipFree(ctx->assembled);
   if (ctx->partials) (void)hipFree(ctx->partials);
   if (ctx->scan) (void)hipFree(ctx->scan);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -443,10 +725,11 @@ int magnus_check(magnus_ctx* ctx, magnus_stream stream) {
   if (!ctx) return fail(MAGNUS_EINVAL, "null context");
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(ctx->device));
-  Slot hs;
-  HIP_TRY(hipMemcpyAsync(&hs, ctx->slots, sizeof(Slot), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (hs.status & 1) return fail(MAGNUS_ENAN, "non-finite vector norm met on the device");
+  long long iters = 0;
+  int status = 0;
+  int rc = read_slots(ctx, s, &iters, &status);
+  if (rc) return rc;
+  if (status & 1) return fail(MAGNUS_ENAN, "non-finite vector norm met on the device");
   return MAGNUS_OK;
 }
 
@@ -498,9 +781,16 @@ int expmv_leja(magnus_ctx* ctx, const magnus_hamiltonian* h, double a, double b,
   acc.products_per_iter = kappa != 0.0 ? 4 : 2;
   const double2* vin = reinterpret_cast<const double2*>(v);
   double2* wout = reinterpret_cast<double2*>(w);
-  for (int32_t c = 0; c < batch; ++c) {
-    rc = run_exponential(ctx, ExpOp{h, a, b, kappa}, tau, vin + c * dim, wout + c * dim, tol_e, opts, &acc, s);
+  for (int32_t c = 0; c < batch;) {
+    const int g = (multi_ok(h, kappa) && tau != 0.0) ? group_for(h, batch - c) : 1;
+    if (g > 1) {
+      std::vector<double> av(g, a), bv(g, b);
+      rc = multi_expmv_group(ctx, h, g, av.data(), bv.data(), tau, vin + c * dim, wout + c * dim, tol_e, opts, &acc, s);
+    } else {
+      rc = run_exponential(ctx, ExpOp{h, a, b, kappa}, tau, vin + c * dim, wout + c * dim, tol_e, opts, &acc, s);
+    }
     if (rc) return rc;
+    c += g;
   }
   return end_call(ctx, acc, tol_e, stats, s);
 }
@@ -523,10 +813,20 @@ static int step_common(int method, magnus_ctx* ctx, const magnus_hamiltonian* h,
   acc.products_per_iter = method == MAGNUS_M4 ? 4 : 2;
   const double2* in = reinterpret_cast<const double2*>(psi_in);
   double2* out = reinterpret_cast<double2*>(psi_out);
-  for (int32_t c = 0; c < batch; ++c) {
-    rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s)
-                                : m4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s);
+  for (int32_t c = 0; c < batch;) {
+    const int g = (method == MAGNUS_CF4 && multi_ok(h, 0.0)) ? group_for(h, batch - c) : 1;
+    if (g > 1) {
+      HIP_TRY(magnus::launch_pack(in + c * dim, ctx->vec(kY), (int)dim, g, s));
+      rc = multi_cf4_steps(ctx, h, g, tau, 0, 1, [&](int, int64_t, int j) { return j == 0 ? f1 : f2; }, tol_e, opts,
+                           &acc, s);
+      if (rc) return rc;
+      HIP_TRY(magnus::launch_unpack(ctx->vec(kY), out + c * dim, (int)dim, g, s));
+    } else {
+      rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s)
+                                  : m4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s);
+    }
     if (rc) return rc;
+    c += g;
   }
   return end_call(ctx, acc, tol_e, stats, s);
 }
@@ -572,16 +872,40 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
   const int64_t nck = checkpoints ? (nsteps + every_k - 1) / every_k + 1 : 0;
   const size_t stride = (size_t)dim * (size_t)batch;
   if (ck) HIP_TRY(hipMemcpyAsync(ck, st, sizeof(double2) * stride, hipMemcpyDeviceToDevice, s));
-  for (int64_t n = 0; n < nsteps; ++n) {
-    for (int32_t c = 0; c < batch; ++c) {
-      const double* fn = f_nodes + ((batch_f == 1 ? 0 : (int64_t)c) * nsteps + n) * 2;
-      double2* y = st + c * dim;
-      rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, fn[0], fn[1], y, y, tol_e, opts, &acc, s)
-                                  : m4_state(ctx, h, tau, fn[0], fn[1], y, y, tol_e, opts, &acc, s);
-      if (rc) return rc;
+  auto fval = [&](int c, int64_t n, int j) {
+    return f_nodes[((batch_f == 1 ? 0 : (int64_t)c) * nsteps + n) * 2 + j];
+  };
+  const bool grouped = method == MAGNUS_CF4 && multi_ok(h, 0.0) && batch > 1;
+  // checkpoint steps: multiples of every_k and the last step
+  auto next_stop = [&](int64_t n) {
+    if (!ck) return nsteps;
+    const int64_t k = ((n / every_k) + 1) * every_k;
+    return std::min(k, nsteps);
+  };
+  int64_t n = 0;
+  while (n < nsteps) {
+    const int64_t stop = next_stop(n);
+    for (int32_t c = 0; c < batch;) {
+      const int g = grouped ? group_for(h, batch - c) : 1;
+      if (g > 1) {
+        HIP_TRY(magnus::launch_pack(st + c * dim, ctx->vec(kY), (int)dim, g, s));
+        rc = multi_cf4_steps(ctx, h, g, tau, n, stop,
+                             [&](int cc, int64_t k, int j) { return fval(c + cc, k, j); }, tol_e, opts, &acc, s);
+        if (rc) return rc;
+        HIP_TRY(magnus::launch_unpack(ctx->vec(kY), st + c * dim, (int)dim, g, s));
+      } else {
+        for (int64_t k = n; k < stop; ++k) {
+          double2* y = st + c * dim;
+          rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, fval(c, k, 0), fval(c, k, 1), y, y, tol_e, opts, &acc, s)
+                                      : m4_state(ctx, h, tau, fval(c, k, 0), fval(c, k, 1), y, y, tol_e, opts, &acc, s);
+          if (rc) return rc;
+        }
+      }
+      c += g;
     }
-    if (ck && ((n + 1) % every_k == 0 || n + 1 == nsteps)) {
-      const int64_t slot = (n + 1) % every_k == 0 ? (n + 1) / every_k : nck - 1;
+    n = stop;
+    if (ck) {
+      const int64_t slot = n % every_k == 0 ? n / every_k : nck - 1;
       HIP_TRY(hipMemcpyAsync(ck + slot * stride, st, sizeof(double2) * stride, hipMemcpyDeviceToDevice, s));
     }
   }
@@ -602,7 +926,7 @@ int magnus_timing(magnus_ctx* ctx, int32_t enable) {
 
 int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches) {
   if (!ctx || !total_ms || !launches) return fail(MAGNUS_EINVAL, "null argument");
-  if (kind < MAGNUS_KERNEL_CSR_LEJA || kind > MAGNUS_KERNEL_DENSE_LEJA) return fail(MAGNUS_EINVAL, "kernel class %d", kind);
+  if (kind < MAGNUS_KERNEL_CSR_LEJA || kind > MAGNUS_KERNEL_DENSE_MFMA) return fail(MAGNUS_EINVAL, "kernel class %d", kind);
   HIP_TRY(hipSetDevice(ctx->device));
   double t = 0.0;
   int64_t n = 0;
@@ -617,6 +941,137 @@ int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t*
   *total_ms = t;
   *launches = n;
   return MAGNUS_OK;
+}
+
+int64_t magnus_adjoint_workspace_bytes(int64_t dim, int64_t nsteps, int32_t every_k) {
+  if (dim < 1 || nsteps < 1 || every_k < 1) return -1;
+  const int64_t k = std::min<int64_t>(every_k, nsteps);
+  const int64_t nck = (nsteps + k - 1) / k + 1;
+  const int64_t vecs = nck + (k + 1) + k + 2 + 4;
+  return (vecs * dim + 2 * nsteps + 1) * (int64_t)sizeof(double2);
+}
+
+int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, int64_t nsteps,
+                             const double* f_nodes, const double* df_nodes, int32_t nparams, const void* psi0,
+                             const void* psi_target, int32_t every_k, void* workspace, int64_t workspace_bytes,
+                             double* loss, double* grad, const magnus_leja_opts* opts, magnus_stats* stats,
+                             magnus_stream stream) {
+  int rc = check_ham(ctx, h, 0);
+  if (rc) return rc;
+  if ((rc = check_opts(opts))) return rc;
+  if (h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "the adjoint needs CSR terms");
+  if (ctx->max_batch < 2) return fail(MAGNUS_ENOMEM, "the adjoint needs a context with max_batch >= 2");
+  if (nsteps < 1 || nparams < 0 || every_k < 1) return fail(MAGNUS_EINVAL, "nsteps, nparams or every_k out of range");
+  if (!f_nodes || (nparams > 0 && !df_nodes) || !psi0 || !psi_target || !workspace || !loss || (nparams > 0 && !grad))
+    return fail(MAGNUS_EINVAL, "null argument");
+  if (!is_fin(tau)) return fail(MAGNUS_EDOMAIN, "non-finite step");
+  for (int64_t i = 0; i < 2 * nsteps; ++i)
+    if (!is_fin(f_nodes[i])) return fail(MAGNUS_EDOMAIN, "non-finite field value");
+  for (int64_t i = 0; i < 2 * nsteps * (int64_t)nparams; ++i)
+    if (!is_fin(df_nodes[i])) return fail(MAGNUS_EDOMAIN, "non-finite field derivative");
+  const int64_t need = magnus_adjoint_workspace_bytes(h->H1.dim, nsteps, every_k);
+  if (workspace_bytes < need)
+    return fail(MAGNUS_ENOMEM, "workspace of %lld bytes, need %lld", (long long)workspace_bytes, (long long)need);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = begin_call(ctx, s))) return rc;
+  if ((rc = ensure_valid(ctx, h, s))) return rc;
+
+  const int64_t dim = h->H1.dim;
+  const int64_t k = std::min<int64_t>(every_k, nsteps);
+  const int64_t nck = (nsteps + k - 1) / k + 1;
+  const int64_t nseg = (nsteps + k - 1) / k;
+  double2* base = reinterpret_cast<double2*>(workspace);
+  double2* ck = base;                       // nck states
+  double2* seg_psi = ck + nck * dim;        // k + 1 states
+  double2* seg_phi = seg_psi + (k + 1) * dim;  // k states
+  double2* lam = seg_phi + k * dim;
+  double2* mu = lam + dim;
+  double2* X2 = mu + dim;                   // interleaved pair
+  double2* Y2 = X2 + 2 * dim;
+  double2* g = Y2 + 2 * dim;                // 2 nsteps + 1 complex
+  const double tol_e = per_exp_tol(opts, 2 * nsteps);
+  Acc acc;
+  auto beta_of = [&](int64_t n) { return magnus::kAlpha2 * f_nodes[2 * n] + magnus::kAlpha1 * f_nodes[2 * n + 1]; };
+  auto gamma_of = [&](int64_t n) { return magnus::kAlpha1 * f_nodes[2 * n] + magnus::kAlpha2 * f_nodes[2 * n + 1]; };
+  const double2* tgt = reinterpret_cast<const double2*>(psi_target);
+
+  // forward sweep with checkpoints (state kept in mu)
+  HIP_TRY(hipMemcpyAsync(ck, psi0, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(mu, psi0, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
+  for (int64_t n = 0; n < nsteps; ++n) {
+    rc = cf4_state(ctx, h, tau, f_nodes[2 * n], f_nodes[2 * n + 1], mu, mu, tol_e, opts, &acc, s);
+    if (rc) return rc;
+    if ((n + 1) % k == 0 || n + 1 == nsteps) {
+      const int64_t slot = (n + 1) % k == 0 ? (n + 1) / k : nck - 1;
+      HIP_TRY(hipMemcpyAsync(ck + slot * dim, mu, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  HIP_TRY(magnus::launch_cdot(tgt, 1, mu, 1, dim, ctx->partials, g + 2 * nsteps, s));
+  HIP_TRY(hipMemcpyAsync(lam, tgt, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
+
+  const double half[2] = {0.5, 0.5};
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t n0 = seg * k, n1 = std::min(n0 + k, nsteps);
+    // recompute psi_n and the half-step states phi_n of the segment
+    HIP_TRY(hipMemcpyAsync(seg_psi, ck + seg * dim, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
+    for (int64_t n = n0; n < n1; ++n) {
+      double2* p0 = seg_psi + (n - n0) * dim;
+      double2* ph = seg_phi + (n - n0) * dim;
+      rc = run_exponential(ctx, ExpOp{h, 0.5, beta_of(n), 0.0}, tau, p0, ph, tol_e, opts, &acc, s);
+      if (rc) return rc;
+      rc = run_exponential(ctx, ExpOp{h, 0.5, gamma_of(n), 0.0}, tau, ph, p0 + dim, tol_e, opts, &acc, s);
+      if (rc) return rc;
+    }
+    // block (Frechet) exponentials of the segment, planned and uploaded together
+    std::vector<ColParam> table;
+    std::vector<MultiExp> ea(n1 - n0), eb(n1 - n0);
+    for (int64_t n = n0; n < n1; ++n) {
+      const double ga2[2] = {gamma_of(n), gamma_of(n)}, be2[2] = {beta_of(n), beta_of(n)};
+      rc = plan_multi(h, half, ga2, 2, tau, tol_e, opts, 1, &table, &ea[n - n0], &acc);
+      if (rc) return rc;
+      rc = plan_multi(h, half, be2, 2, tau, tol_e, opts, 1, &table, &eb[n - n0], &acc);
+      if (rc) return rc;
+    }
+    if ((rc = upload_table(ctx, table, s))) return rc;
+    for (int64_t n = n1 - 1; n >= n0; --n) {
+      MultiExp A = ea[n - n0], Bx = eb[n - n0];
+      A.src = X2;
+      A.dst = Y2;
+      Bx.src = X2;
+      Bx.dst = Y2;
+      // g_a(n) = lambda_{n+1}^H L_a phi_n
+      HIP_TRY(magnus::launch_frechet_init(seg_phi + (n - n0) * dim, X2, (int)dim, s));
+      if ((rc = launch_multi(ctx, h, A, tol_e, opts->early_termination, s))) return rc;
+      HIP_TRY(magnus::launch_cdot(lam, 1, Y2, 2, dim, ctx->partials, g + 2 * n, s));
+      // mu_n = E_a^H lambda_{n+1}
+      rc = run_exponential(ctx, ExpOp{h, 0.5, gamma_of(n), 0.0}, -tau, lam, mu, tol_e, opts, &acc, s);
+      if (rc) return rc;
+      // g_b(n) = mu_n^H L_b psi_n
+      HIP_TRY(magnus::launch_frechet_init(seg_psi + (n - n0) * dim, X2, (int)dim, s));
+      if ((rc = launch_multi(ctx, h, Bx, tol_e, opts->early_termination, s))) return rc;
+      HIP_TRY(magnus::launch_cdot(mu, 1, Y2, 2, dim, ctx->partials, g + 2 * n + 1, s));
+      // lambda_n = E_b^H mu_n
+      rc = run_exponential(ctx, ExpOp{h, 0.5, beta_of(n), 0.0}, -tau, mu, lam, tol_e, opts, &acc, s);
+      if (rc) return rc;
+    }
+  }
+  std::vector<double2> hg(2 * nsteps + 1);
+  HIP_TRY(hipMemcpyAsync(hg.data(), g, sizeof(double2) * hg.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const std::complex<double> z(hg[2 * nsteps].x, hg[2 * nsteps].y);
+  *loss = 1.0 - std::norm(z);
+  for (int32_t p = 0; p < nparams; ++p) {
+    std::complex<double> dz = 0.0;
+    for (int64_t n = 0; n < nsteps; ++n) {
+      const double d1 = df_nodes[(2 * n) * nparams + p], d2v = df_nodes[(2 * n + 1) * nparams + p];
+      const double dbeta = magnus::kAlpha2 * d1 + magnus::kAlpha1 * d2v;
+      const double dgamma = magnus::kAlpha1 * d1 + magnus::kAlpha2 * d2v;
+      dz += dgamma * std::complex<double>(hg[2 * n].x, hg[2 * n].y) +
+            dbeta * std::complex<double>(hg[2 * n + 1].x, hg[2 * n + 1].y);
+    }
+    grad[p] = -2.0 * std::real(std::conj(z) * dz);
+  }
+  return end_call(ctx, acc, tol_e, stats, s);
 }
 
 int magnus_quadrature_nodes(int32_t method, double t0, double tau, int64_t nsteps, double* t_out) {

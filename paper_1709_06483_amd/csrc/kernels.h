@@ -91,6 +91,66 @@ int dense2_grid(int dim);
 // workgroups) and write the early-termination verdict into the slot.
 hipError_t launch_leja_decide(const IterArgs& a, int grid, hipStream_t s);
 
+// ---- several states at once (states interleaved: element (row, b) at row*B + b) ----
+
+constexpr int kMaxCols = 32;
+
+// Leja parameters of one state (column) for one iteration.
+struct ColParam {
+  double a1, a2;        // scale * a, scale * b
+  double sigma;         // scale * c + xi_{i-1}
+  double dre, dim;      // d_i
+  double dabs;          // |d_i|
+  double d0re, d0im;    // d_0
+  double d0abs;         // |d_0|
+  double coup;          // Frechet coupling (scale * 1 for the H2 block), 0 otherwise
+};
+
+struct MultiArgs {
+  const double2* x;     // w_{i-1} (v on the first iteration), interleaved
+  double2* wout;        // w_i
+  double2* pacc;        // p
+  Slot* slots;          // one per column
+  double* partials;     // [grid][B][2]
+  const ColParam* prm;  // B entries for this iteration
+  int B;
+  int first;
+  int check_stop;
+  int early;
+  double tol;
+  int joint;            // 1: the B columns form one block vector (shared stop test)
+};
+
+enum MultiMode : int { kMultiLeja = 0, kMultiFrechet = 1 };
+
+int csr2_multi_grid(int dim, int B);
+// One Leja iteration for B interleaved states sharing H1, H2 (B in 2, 4, 8, 16, 32).
+// kMultiFrechet (B == 2): columns (x, y) of the block vector of [[H, H2], [0, H]].
+hipError_t launch_csr2_multi(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const MultiArgs& a,
+                             hipStream_t s);
+// Per-column (or joint) reduction of the partials and stop verdicts.
+hipError_t launch_multi_decide(const MultiArgs& a, int grid, hipStream_t s);
+// Interleave / de-interleave B states of dim entries (optionally scaling by a
+// per-state phase is not needed: plain copies).
+hipError_t launch_pack(const double2* src, double2* dst, int dim, int B, hipStream_t s);
+hipError_t launch_unpack(const double2* src, double2* dst, int dim, int B, hipStream_t s);
+
+// Dense group iteration as an FP64 MFMA GEMM fused with the Leja update
+// (nterms = 1: H1 only, y_b = a1_b H1 w_b; nterms = 2: y_b = H1 (a1_b w_b) + H2 (a2_b w_b)).
+// Partials are written per 32-row block: decide with dense_mfma_row_blocks(dim).
+hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
+                             const MultiArgs& a, hipStream_t s);
+int dense_mfma_row_blocks(int dim);
+// out = ca H1 + cb H2 (dim x dim, row stride ld in, dim out).
+hipError_t launch_dense_assemble(const double2* H1, const double2* H2, long long ld, int dim, double ca, double cb,
+                                 double2* out, hipStream_t s);
+
+// out = sum_i conj(x[i*sx]) y[i*sy] (fixed order; partials: 1024 doubles).
+hipError_t launch_cdot(const double2* x, long long sx, const double2* y, long long sy, long long n, double* partials,
+                       double2* out, hipStream_t s);
+// dst (interleaved pair) = [0; v].
+hipError_t launch_frechet_init(const double2* v, double2* dst, int dim, hipStream_t s);
+
 // Small helpers.
 hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_t s);
 hipError_t launch_slot_reset(Slot* slot, int n, hipStream_t s);

@@ -670,7 +670,7 @@ __global__ void copy_kernel(const double2* __restrict__ src, double2* __restrict
 }
 
 __global__ void slot_reset_kernel(Slot* s, int n) {
-  const int i = threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     s[i].counter = 0u;
     s[i].stopped = 0;
@@ -769,7 +769,7 @@ hipError_t launch_leja_decide(const IterArgs& a, int grid, hipStream_t s) {
 }
 
 hipError_t launch_slot_reset(Slot* slot, int n, hipStream_t s) {
-  slot_reset_kernel<<<1, 64, 0, s>>>(slot, n);
+  slot_reset_kernel<<<(n + 63) / 64, 64, 0, s>>>(slot, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,215 @@
+// Dense Leja iteration for a group of states: Y = H W as an FP64 MFMA GEMM
+// (gfx950 v_mfma_f64_16x16x4f64), fused with the Leja update.
+//
+// W holds B states interleaved (element (k, b) at k * B + b); H is row-major.
+// The complex product uses four real MFMAs per 16x16x4 step:
+//   Yre += Hre Wre - Him Wim,   Yim += Hre Wim + Him Wre.
+// NT = 1: one (assembled) matrix, y_b = a1_b (H w_b).
+// NT = 2: two terms with per-state coefficients folded into the W operand,
+//         y_b = H1 (a1_b w_b) + H2 (a2_b w_b).
+// A wave computes a 16 x 32 output tile (1 x 2 MFMA tiles), a workgroup of
+// four waves 32 rows x 64 states; K is staged through LDS 16 at a time with
+// the next chunk prefetched into registers while the MFMAs run.
+#include "device_common.h"
+
+namespace magnus {
+namespace {
+
+using namespace dev;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 32, TN = 64, TK = 16;
+constexpr int WM = 16, WN = 32;   // wave tile
+constexpr int TJ = WN / 16;       // MFMA tiles per wave along the states
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2* H1, const double2* H2,
+                                                                  long long ld, int dim, MultiArgs a) {
+  __shared__ double sHre[NT][TM][TK + 1], sHim[NT][TM][TK + 1];
+  __shared__ double sWre[TK][TN + 1], sWim[TK][TN + 1];
+  __shared__ double csum[2][2][TN];  // [row half][w|v][state]
+  __shared__ int sstop_any;
+  const int B = a.B;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv >> 1, wc = wv & 1;  // wave position in the 2 x 2 arrangement
+
+  // block coordinates: the column blocks of one row block share an XCD
+  const int gx = (B + TN - 1) / TN;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int rb = L / gx, cb = L % gx;
+  const int row0 = rb * TM, col0 = cb * TN;
+
+  if (tid == 0) {
+    int any_running = 0;
+    for (int c = col0; c < min(B, col0 + TN); ++c)
+      any_running |= a.check_stop ? !load_stopped(&a.slots[c]) : 1;
+    sstop_any = any_running;
+  }
+  __syncthreads();
+  if (!sstop_any) return;  // every state of this block has stopped (uniform)
+
+  // per-lane operand scale factors (NT = 2): columns of this lane's B operands
+  double sc[NT][TJ];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    const int c = col0 + wc * WN + tj * 16 + (lane & 15);
+    const ColParam P = a.prm[c < B ? c : 0];
+    sc[0][tj] = NT == 2 ? P.a1 : 1.0;
+    if constexpr (NT == 2) sc[1][tj] = P.a2;
+  }
+
+  // staging assignment: H tile TM x TK per term (2 complex per thread),
+  // W tile TK x TN (4 complex per thread)
+  const int h_r = tid >> 3, h_k = (tid & 7) * 2;         // 32 rows x 8 pairs
+  const int w_k = tid >> 4, w_c = (tid & 15) * 4;        // 16 k x 16 quads
+  const d2* W = reinterpret_cast<const d2*>(a.x);
+  const d2* Hp[2] = {reinterpret_cast<const d2*>(H1), reinterpret_cast<const d2*>(H2)};
+  d2 hreg[NT][2], wreg[4];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = row0 + h_r, k = k0 + h_k + u;
+        hreg[t][u] = (r < dim && k < dim) ? __builtin_nontemporal_load(Hp[t] + (long long)r * ld + k) : d2{0.0, 0.0};
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + w_k, c = col0 + w_c + u;
+      wreg[u] = (k < dim && c < B) ? W[(long long)k * B + c] : d2{0.0, 0.0};
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        sHre[t][h_r][h_k + u] = hreg[t][u].x;
+        sHim[t][h_r][h_k + u] = hreg[t][u].y;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sWre[w_k][w_c + u] = wreg[u].x;
+      sWim[w_k][w_c + u] = wreg[u].y;
+    }
+  };
+
+  v4d are[TJ], aim[TJ];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    are[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+    aim[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  const int nk = (dim + TK - 1) / TK;
+  load_chunk(0);
+  for (int kc = 0; kc < nk; ++kc) {
+    __syncthreads();  // previous chunk's operands consumed
+    store_chunk();
+    __syncthreads();
+    if (kc + 1 < nk) load_chunk((kc + 1) * TK);  // in flight during the MFMAs
+#pragma unroll
+    for (int ks = 0; ks < TK / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      const int ar = wr * WM + (lane & 15);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double hre = sHre[t][ar][kk], him = sHim[t][ar][kk];
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+          const int bc = wc * WN + tj * 16 + (lane & 15);
+          const double wre = sWre[kk][bc] * sc[t][tj], wim = sWim[kk][bc] * sc[t][tj];
+          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wre, are[tj], 0, 0, 0);
+          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-him, wim, are[tj], 0, 0, 0);
+          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wim, aim[tj], 0, 0, 0);
+          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(him, wre, aim[tj], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // epilogue: accumulator element j of a lane is row lane/16 + 4 j of its
+  // 16-row tile, state lane % 16 (the v_mfma_f64_16x16x4f64 output layout)
+  double pw[TJ], pv[TJ];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    pw[tj] = 0.0;
+    pv[tj] = 0.0;
+    const int c = col0 + wc * WN + tj * 16 + (lane & 15);
+    if (c >= B) continue;
+    const ColParam P = a.prm[c];
+    const bool stopped_c = a.check_stop ? load_stopped(&a.slots[c]) != 0 : false;
+    const double ys = NT == 2 ? 1.0 : P.a1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = row0 + wr * WM + (lane >> 4) + 4 * j;
+      if (r >= dim) continue;
+      const long long idx = (long long)r * B + c;
+      const d2 y = d2{ys * are[tj][j], ys * aim[tj][j]};
+      const d2 w_old = W[idx];
+      const d2 wn = y - rmul(P.sigma, w_old);
+      const d2 dd = {P.dre, P.dim};
+      d2 p;
+      if (a.first) {
+        p = cmul(d2{P.d0re, P.d0im}, w_old) + cmul(dd, wn);
+        pv[tj] += nrm2(w_old);
+      } else {
+        p = tod2(a.pacc[idx]);
+        if (!stopped_c) p += cmul(dd, wn);
+      }
+      a.wout[idx] = fromd2(wn);
+      a.pacc[idx] = fromd2(p);
+      pw[tj] += nrm2(wn);
+    }
+  }
+  // per-state sums: lanes l, l + 16, l + 32, l + 48 share a state
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    pw[tj] += __shfl_xor(pw[tj], 16, 64);
+    pw[tj] += __shfl_xor(pw[tj], 32, 64);
+    pv[tj] += __shfl_xor(pv[tj], 16, 64);
+    pv[tj] += __shfl_xor(pv[tj], 32, 64);
+    if (lane < 16) {
+      csum[wr][0][wc * WN + tj * 16 + lane] = pw[tj];
+      csum[wr][1][wc * WN + tj * 16 + lane] = pv[tj];
+    }
+  }
+  __syncthreads();
+  if (tid < TN && col0 + tid < B) {
+    const long long o = ((long long)rb * B + col0 + tid) * 2;
+    a.partials[o] = csum[0][0][tid] + csum[1][0][tid];
+    a.partials[o + 1] = csum[0][1][tid] + csum[1][1][tid];
+  }
+}
+
+// H = a H1 + b H2 (row-major, row stride ld in, dim out).
+__global__ void dense_assemble_kernel(const double2* __restrict__ H1, const double2* __restrict__ H2, long long ld,
+                                      int dim, double ca, double cb, double2* __restrict__ out) {
+  const long long n = (long long)dim * dim;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / dim, c = i % dim;
+    const d2 x = __builtin_nontemporal_load(reinterpret_cast<const d2*>(H1) + r * ld + c);
+    const d2 y = __builtin_nontemporal_load(reinterpret_cast<const d2*>(H2) + r * ld + c);
+    out[i] = fromd2(rmul(ca, x) + rmul(cb, y));
+  }
+}
+
+}  // namespace
+
+int dense_mfma_row_blocks(int dim) { return (dim + TM - 1) / TM; }
+
+hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
+                             const MultiArgs& a, hipStream_t s) {
+  const int gx = (a.B + TN - 1) / TN;
+  const int grid = dense_mfma_row_blocks(dim) * gx;
+  if (nterms == 1) dense_mfma_leja_kernel<1><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
+  else dense_mfma_leja_kernel<2><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_assemble(const double2* H1, const double2* H2, long long ld, int dim, double ca, double cb,
+                                 double2* out, hipStream_t s) {
+  dense_assemble_kernel<<<4096, kThreads, 0, s>>>(H1, H2, ld, dim, ca, cb, out);
+  return hipGetLastError();
+}
+
+}  // namespace magnus

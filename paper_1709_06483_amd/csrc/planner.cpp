@@ -106,8 +106,10 @@ struct Tables {
   HTable H;
   std::vector<double> basis;      // [k][x]: prod_{j<k} (x - xi_j) on the x grid
   std::vector<double> basis_max;  // [k]: max_x |basis[k][x]|
+  std::vector<double> basis_der;  // [k][x]: d/dx prod_{j<k} (x - xi_j)
   std::vector<double> thetas;     // grid
   std::vector<double> epsmax;     // [g][m], running max over theta_g' <= theta_g
+  std::vector<double> epsder;     // [g][m], same for the derivative of the error
 };
 
 void dd_long(const Tables& T, double theta, int m, std::complex<long double>* d) {
@@ -125,12 +127,15 @@ void dd_long(const Tables& T, double theta, int m, std::complex<long double>* d)
   }
 }
 
-double tail_error(const Tables& T, double theta, int m, std::vector<double>* eps_all) {
-  // eps_all[m'] for every m' <= kMaxDegree when eps_all != nullptr
+double tail_error(const Tables& T, double theta, int m, std::vector<double>* eps_all,
+                  std::vector<double>* der_all = nullptr) {
+  // eps_all[m'] (and der_all[m'], the sup of the derivative of the error) for
+  // every m' <= kMaxDegree when requested
   const int K = kNumPoints - 1;
   std::vector<std::complex<long double>> dl(K + 1);
   dd_long(T, theta, K, dl.data());
-  std::vector<double> tr(kXGrid, 0.0), ti(kXGrid, 0.0);
+  std::vector<double> tr(kXGrid, 0.0), ti(kXGrid, 0.0), ur(kXGrid, 0.0), ui(kXGrid, 0.0);
+  if (der_all) der_all->assign(kMaxDegree + 1, 0.0);
   double result = 0.0;
   if (eps_all) eps_all->assign(kMaxDegree + 1, 0.0);
   // terms whose size is far below any representable error contribute nothing
@@ -149,6 +154,16 @@ double tail_error(const Tables& T, double theta, int m, std::vector<double>* eps
     const int mm = k - 1;  // the tail k..K is the error of degree k-1
     if (mm == m) result = std::sqrt(mx);
     if (eps_all && mm <= kMaxDegree) (*eps_all)[mm] = std::sqrt(mx);
+    if (der_all) {
+      const double* bd = &T.basis_der[(size_t)k * kXGrid];
+      double md = 0.0;
+      for (int x = 0; x < kXGrid; ++x) {
+        ur[x] += dr * bd[x];
+        ui[x] += di * bd[x];
+        md = std::max(md, ur[x] * ur[x] + ui[x] * ui[x]);
+      }
+      if (mm <= kMaxDegree) (*der_all)[mm] = std::sqrt(md);
+    }
   }
   return result;
 }
@@ -166,6 +181,14 @@ Tables* build_tables() {
       p *= (xv - T->xi[k]);
     }
   }
+  T->basis_der.assign((size_t)kNumPoints * kXGrid, 0.0);
+  for (int x = 0; x < kXGrid; ++x) {
+    const double xv = -2.0 + 4.0 * x / (kXGrid - 1);
+    // (P_{k+1})' = (P_k)' (x - xi_k) + P_k
+    for (int k = 0; k + 1 < kNumPoints; ++k)
+      T->basis_der[(size_t)(k + 1) * kXGrid + x] =
+          T->basis_der[(size_t)k * kXGrid + x] * (xv - T->xi[k]) + T->basis[(size_t)k * kXGrid + x];
+  }
   T->basis_max.assign(kNumPoints, 0.0);
   for (int k = 0; k < kNumPoints; ++k)
     for (int x = 0; x < kXGrid; ++x)
@@ -175,13 +198,18 @@ Tables* build_tables() {
   if (T->thetas.back() < kThetaCap) T->thetas.push_back(kThetaCap);
   const size_t G = T->thetas.size();
   T->epsmax.assign(G * (kMaxDegree + 1), 0.0);
-  std::vector<double> e;
+  T->epsder.assign(G * (kMaxDegree + 1), 0.0);
+  std::vector<double> e, ed;
   for (size_t g = 0; g < G; ++g) {
-    tail_error(*T, T->thetas[g], -1, &e);
+    tail_error(*T, T->thetas[g], -1, &e, &ed);
     for (int m = 0; m <= kMaxDegree; ++m) {
-      double v = e[m];
-      if (g > 0) v = std::max(v, T->epsmax[(g - 1) * (kMaxDegree + 1) + m]);
+      double v = e[m], w = ed[m];
+      if (g > 0) {
+        v = std::max(v, T->epsmax[(g - 1) * (kMaxDegree + 1) + m]);
+        w = std::max(w, T->epsder[(g - 1) * (kMaxDegree + 1) + m]);
+      }
       T->epsmax[g * (kMaxDegree + 1) + m] = v;
+      T->epsder[g * (kMaxDegree + 1) + m] = w;
     }
   }
   return T;
@@ -242,6 +270,34 @@ bool plan_degree(double theta, double tol, int max_degree, int max_substeps, Lej
   return found;
 }
 
+int degree_for_substeps(double theta, double tol, int s, int max_degree, double* bound, double der_weight) {
+  const Tables& T = tables();
+  theta = std::fabs(theta);
+  max_degree = std::min(max_degree, kMaxDegree);
+  if (s < 1) return -1;
+  if (theta == 0.0) { if (bound) *bound = 0.0; return 1; }
+  const double ths = theta / s;
+  if (ths > kThetaCap * (1.0 + 1e-12)) return -1;
+  size_t g = std::lower_bound(T.thetas.begin(), T.thetas.end(), ths * (1.0 - 1e-13)) - T.thetas.begin();
+  if (g >= T.thetas.size()) g = T.thetas.size() - 1;
+  const double target = tol / (2.0 * s);
+  for (int m = 1; m <= max_degree; ++m) {
+    const double e = T.epsmax[g * (kMaxDegree + 1) + m] + der_weight * T.epsder[g * (kMaxDegree + 1) + m];
+    if (e <= target) {
+      if (bound) *bound = s * e;
+      return m;
+    }
+  }
+  return -1;
+}
+
+double leja_derivative_error(double theta, int m) {
+  if (m < 0 || m > kMaxDegree) return std::numeric_limits<double>::infinity();
+  std::vector<double> e, ed;
+  tail_error(tables(), std::fabs(theta), -1, &e, &ed);
+  return ed[m];
+}
+
 void weyl_interval(double a, double l1, double u1, double b, double l2, double u2, double k,
                    double l3, double u3, double* lo, double* hi) {
   auto lo_of = [](double c, double l, double u) { return c >= 0 ? c * l : c * u; };
@@ -250,22 +306,45 @@ void weyl_interval(double a, double l1, double u1, double b, double l2, double u
   *hi = hi_of(a, l1, u1) + hi_of(b, l2, u2) + (k != 0.0 ? hi_of(k, l3, u3) : 0.0);
 }
 
+namespace {
+void finish_plan(double tau, ExpPlan* p) {
+  p->tau_sub = tau / p->lp.s;
+  const double theta_s = p->theta / p->lp.s;
+  std::vector<std::complex<double>> d(p->lp.m + 1);
+  divided_differences(theta_s, p->lp.m, d.data());
+  const std::complex<double> phase = std::polar(1.0, -p->tau_sub * p->c);
+  p->d.resize(p->lp.m + 1);
+  for (int k = 0; k <= p->lp.m; ++k) p->d[k] = phase * d[k];
+}
+
+void centre_and_radius(double tau, double lo, double hi, ExpPlan* p) {
+  p->c = 0.5 * (lo + hi);
+  // widening an enclosure is always safe; keep r away from zero
+  p->r = std::max(0.5 * (hi - lo), 1e-8 * std::max(1.0, std::fabs(p->c)));
+  p->scale = 2.0 / p->r;
+  p->theta = 0.5 * tau * p->r;
+}
+}  // namespace
+
+bool plan_exponential_fixed_s(double tau, double lo, double hi, double tol, int s, int max_degree,
+                              ExpPlan* out, double coupling_norm) {
+  ExpPlan p;
+  centre_and_radius(tau, lo, hi, &p);
+  double bound = 0.0;
+  const int m = degree_for_substeps(p.theta, tol, s, max_degree, &bound, p.scale * coupling_norm);
+  if (m < 0) return false;
+  p.lp = LejaPlan{m, s, bound};
+  finish_plan(tau, &p);
+  *out = std::move(p);
+  return true;
+}
+
 bool plan_exponential(double tau, double lo, double hi, double tol, int max_degree,
                       int max_substeps, ExpPlan* out) {
   ExpPlan p;
-  p.c = 0.5 * (lo + hi);
-  // widening an enclosure is always safe; keep r away from zero
-  p.r = std::max(0.5 * (hi - lo), 1e-8 * std::max(1.0, std::fabs(p.c)));
-  p.scale = 2.0 / p.r;
-  p.theta = 0.5 * tau * p.r;
+  centre_and_radius(tau, lo, hi, &p);
   if (!plan_degree(p.theta, tol, max_degree, max_substeps, &p.lp)) return false;
-  p.tau_sub = tau / p.lp.s;
-  const double theta_s = p.theta / p.lp.s;
-  std::vector<std::complex<double>> d(p.lp.m + 1);
-  divided_differences(theta_s, p.lp.m, d.data());
-  const std::complex<double> phase = std::polar(1.0, -p.tau_sub * p.c);
-  p.d.resize(p.lp.m + 1);
-  for (int k = 0; k <= p.lp.m; ++k) p.d[k] = phase * d[k];
+  finish_plan(tau, &p);
   *out = std::move(p);
   return true;
 }

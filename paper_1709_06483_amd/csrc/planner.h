@@ -50,6 +50,18 @@ struct LejaPlan {
 // Plan for |theta| with caps; returns false if the caps cannot reach tol.
 bool plan_degree(double theta, double tol, int max_degree, int max_substeps, LejaPlan* out);
 
+// Smallest degree m <= max_degree with
+//   s * (err(|theta|/s, m) + der_weight * derr(|theta|/s, m)) <= tol / 2
+// for a given substep count s; returns -1 if none (or if |theta|/s > kThetaCap).
+// derr is the sup over [-2, 2] of the derivative of exp(-i theta x) - p_m(x):
+// for the block operator [[X, E], [0, X]] with Hermitian X its upper-right
+// block carries D(f - p_m)(X)[E], which we bound by derr * |E| (der_weight = |E|).
+int degree_for_substeps(double theta, double tol, int s, int max_degree, double* bound,
+                        double der_weight = 0.0);
+
+// sup over x in [-2, 2] of |d/dx (exp(-i theta x) - p_m(x))| (grid sup of the Newton tail).
+double leja_derivative_error(double theta, int m);
+
 // Weyl enclosure of a*[l1,u1] + b*[l2,u2] + k*[l3,u3].
 void weyl_interval(double a, double l1, double u1, double b, double l2, double u2, double k,
                    double l3, double u3, double* lo, double* hi);
@@ -67,6 +79,13 @@ struct ExpPlan {
 // tau: signed step of the exponential; [lo, hi] encloses spec(H_hat).
 bool plan_exponential(double tau, double lo, double hi, double tol, int max_degree,
                       int max_substeps, ExpPlan* out);
+
+// As plan_exponential with the substep count fixed to s (used when several
+// states share one iteration sequence); false if no degree reaches tol.
+// coupling_norm > 0 plans the block exponential of [[H, E], [0, H]] with
+// |E| <= coupling_norm (error of the upper-right block included).
+bool plan_exponential_fixed_s(double tau, double lo, double hi, double tol, int s, int max_degree,
+                              ExpPlan* out, double coupling_norm = 0.0);
 
 // Gauss nodes c_1, c_2 of Methods M4 / Cf4 and the Cf4 weights.
 constexpr double kSqrt3 = 1.7320508075688772935;

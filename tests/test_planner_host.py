@@ -20,7 +20,7 @@ def test_library_exports_every_header_symbol():
     L = B.lib()
     with open(os.path.join(ROOT, "include", "magnus.h")) as fh:
         text = fh.read()
-    declared = set(re.findall(r"^\s*(?:int|double|const char\*|void)\s+(\w+)\s*\(", text, re.M))
+    declared = set(re.findall(r"^\s*(?:int64_t|int|double|const char\*|void)\s+(\w+)\s*\(", text, re.M))
     assert declared == set(B.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
