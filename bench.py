@@ -54,6 +54,10 @@ def main():
     ap.add_argument("--no-m4", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--workload", default="chain_n20",
+                    choices=["chain_n20", "chain_n10", "dense_8192", "batched_dense_4096", "ragged_chains",
+                             "adjoint_chain_n16"],
+                    help="chain_n20 is the headline line; the others print one informational line each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -83,6 +87,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": True, "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                           "copies": 3}), flush=True)
+        return
+
+    if args.workload != "chain_n20":
+        other_workload(args.workload, args)
         return
 
     cfg = inputs.CONFIGS["chain_n20"]
@@ -199,6 +207,129 @@ def main():
     line.update(out)
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), out
+
+
+def other_workload(name: str, args):
+    """Informational measurements of the other workloads (one JSON line each)."""
+    import numpy as np
+    import torch
+
+    from paper_1709_06483_amd import binding as B
+    from paper_1709_06483_amd import inputs
+
+    K, W = args.steps, args.warmup
+    line = {"workload": name, "n_gpus": 1, "dtype": "f64", "data": "synthetic"}
+    if name in ("chain_n10", "dense_8192"):
+        if name == "chain_n10":
+            cfg = inputs.CONFIGS["chain_n10"]
+            H1, H2 = inputs.chain_terms(cfg["n"], cfg["J"], cfg["Delta"])
+            dim = 1 << cfg["n"]
+            mk = lambda c: B.DeviceHamiltonian.from_csr(H1, H2)
+            f = inputs.cos_field(cfg["omega"])
+            kind = B.KERNEL_CSR_LEJA
+            it_bytes = csr_iter_bytes(H1.nnz + H2.nnz, dim)
+        else:
+            cfg = inputs.CONFIGS["dense_8192"]
+            dim = cfg["N"]
+            H0 = inputs.powerlaw_hermitian(dim, cfg["alpha"], cfg["seeds"]["H0"])
+            V = inputs.powerlaw_hermitian(dim, cfg["alpha"], cfg["seeds"]["V"])
+            mk = lambda c: B.DeviceHamiltonian.from_dense(H0, V)
+            f = inputs.sin_field(cfg["omega"])
+            kind = B.KERNEL_DENSE_LEJA
+            it_bytes = 32 * dim * dim + 64 * dim
+        ctx = B.Context(max_dim=dim)
+        ham = B.magnus_spectral_bounds(ctx, mk(ctx))
+        tau, nrun = cfg["tau"], cfg["nsteps"]
+        tol_e = cfg["budget_tol"] / (2 * nrun)
+        psi0 = inputs.random_states(dim, seed=cfg["psi_seed"] if "psi_seed" in cfg else cfg["seeds"]["psi"])
+        fn = np.vectorize(f)(B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K))
+        psi = torch.from_numpy(psi0).cuda()
+        B.propagate(ctx, ham, B.CF4, tau, fn[:W], psi, opts=B.leja_opts(tol_e))
+        ctx.timing(True)
+        ms, (_, st) = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, fn[W:], psi, opts=B.leja_opts(tol_e),
+                                                  stats=True))
+        kms, kn = ctx.timing_read(kind)
+        ctx.timing(False)
+        line.update({"metric": "Cf4 Magnus steps/sec", "value": K / (ms * 1e-3), "unit": "steps/s", "steps": K,
+                     "ms_per_step": ms / K, "leja_iters_per_step": st["iters"] / K,
+                     "kernel_avg_us": 1e3 * kms / max(kn, 1),
+                     "kernel_gbps": it_bytes * st["iters"] / max(kms * 1e-3, 1e-12) / 1e9,
+                     "hv_gbps": it_bytes * st["iters"] / (ms * 1e-3) / 1e9, "tol_per_exp": tol_e})
+    elif name == "batched_dense_4096":
+        N, Bn, tau = 4096, 256, 0.005
+        H0 = inputs.powerlaw_hermitian(N, 1.5, 31)
+        V = inputs.powerlaw_hermitian(N, 1.5, 32)
+        ctx = B.Context(max_dim=N, max_batch=Bn)
+        ctx.reserve_dense(N)
+        ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H0, V))
+        psi = torch.from_numpy(inputs.random_states(N, seed=30, batch=Bn)).cuda()
+        f = inputs.sin_field(1.0)
+        fn = np.vectorize(f)(B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K))
+        tol_e = 1e-10 / (2 * 200)
+        B.propagate(ctx, ham, B.CF4, tau, fn[:W], psi, opts=B.leja_opts(tol_e))
+        ctx.timing(True)
+        ms, (_, st) = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, fn[W:], psi, opts=B.leja_opts(tol_e),
+                                                  stats=True))
+        kms, kn = ctx.timing_read(B.KERNEL_DENSE_MFMA)
+        ctx.timing(False)
+        flops = 8.0 * N * N * Bn * kn
+        line.update({"metric": "batched Cf4 Magnus steps/sec (256 states)", "value": K / (ms * 1e-3),
+                     "unit": "steps/s", "steps": K, "ms_per_step": ms / K, "state_steps_per_s": Bn * K / (ms * 1e-3),
+                     "gemm_launches": kn, "gemm_avg_us": 1e3 * kms / max(kn, 1),
+                     "mfma_tflops": flops / max(kms * 1e-3, 1e-12) / 1e12,
+                     "mfma_util_vs_78.6TF": flops / max(kms * 1e-3, 1e-12) / 78.6e12,
+                     "leja_iters_per_step": st["iters"] / (K * Bn)})
+    elif name == "ragged_chains":
+        tau, sizes, per = 0.01, (12, 14, 16, 18), 16
+        ctx = B.Context(max_dim=1 << max(sizes), max_batch=per)
+        probs = []
+        for n in sizes:
+            H1, H2 = inputs.chain_terms(n)
+            ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+            psi = torch.from_numpy(inputs.random_states(1 << n, seed=300 + n, batch=per)).cuda()
+            t = B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K)
+            fn = np.stack([np.vectorize(inputs.cos_field(2.0, 1.0 + k / per))(t) for k in range(per)])
+            probs.append((ham, psi, fn))
+        tol_e = 1e-10 / (2 * 100)
+        for ham, psi, fn in probs:
+            B.propagate(ctx, ham, B.CF4, tau, fn[:, :W], psi, opts=B.leja_opts(tol_e))
+        ms, _ = _timed(lambda: [B.propagate(ctx, ham, B.CF4, tau, fn[:, W:], psi, opts=B.leja_opts(tol_e))
+                                for ham, psi, fn in probs])
+        line.update({"metric": "ragged batch Cf4 Magnus steps/sec (4 sizes x 16 instances)",
+                     "value": K / (ms * 1e-3), "unit": "steps/s", "steps": K, "ms_per_step": ms / K,
+                     "instance_steps_per_s": len(sizes) * per * K / (ms * 1e-3)})
+    elif name == "adjoint_chain_n16":
+        from paper_1709_06483_amd import adjoint as A
+        n, P, T, nsteps = 16, 32, 2.0, 400
+        tau = T / nsteps
+        H1, H2 = inputs.chain_terms(n)
+        ctx = B.Context(max_dim=1 << n, max_batch=2)
+        ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+        theta = inputs.fourier_theta(P, 40)
+        d0 = torch.from_numpy(inputs.random_states(1 << n, seed=41)).cuda()
+        dt = torch.from_numpy(inputs.random_states(1 << n, seed=42)).cuda()
+        prob = A.ControlProblem.with_basis(ctx, ham, tau, nsteps, inputs.fourier_basis(P, T), d0, dt, every_k=20,
+                                           opts=B.leja_opts(1e-10 / (2 * nsteps)))
+        prob.loss_and_grad(theta)
+        ms_g, (loss, grad) = _timed(lambda: prob.loss_and_grad(theta))
+        f = prob.basis_nodes @ theta
+        psi = d0.clone()
+        ms_f, _ = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, f, psi, opts=prob.opts))
+        line.update({"metric": "adjoint loss+gradient time vs forward (n=16 chain, 400 Cf4 steps, 32 params)",
+                     "value": ms_g / ms_f, "unit": "ratio", "gradient_ms": ms_g, "forward_ms": ms_f,
+                     "loss": loss, "grad_norm": float(np.linalg.norm(grad))})
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline(H1, H2, f, tau, psi0, nsample: int):
