@@ -237,7 +237,7 @@ def other_workload(name: str, args):
             dim = 1 << cfg["n"]
             mk = lambda c: B.DeviceHamiltonian.from_csr(H1, H2)
             f = inputs.cos_field(cfg["omega"])
-            kind = B.KERNEL_CSR_LEJA
+            kind = B.KERNEL_PERSIST  # 1024 rows: the whole call runs in the one-workgroup-per-state kernel
             it_bytes = csr_iter_bytes(H1.nnz + H2.nnz, dim)
         else:
             cfg = inputs.CONFIGS["dense_8192"]

@@ -54,8 +54,10 @@ extern "C" {
 #define MAGNUS_DENSE  1
 
 /* ---- methods ---------------------------------------------------------------- */
-#define MAGNUS_CF4  0   /* Section 2, Method Cf4 */
-#define MAGNUS_M4   1   /* Section 2, Method M4  */
+#define MAGNUS_CF4  0   /* Section 2, Method Cf4: 2 Gauss nodes, 2 exponentials */
+#define MAGNUS_M4   1   /* Section 2, Method M4: 2 Gauss nodes, 1 exponential with the commutator */
+#define MAGNUS_M2   2   /* Section 2, exponential midpoint rule (order 2): 1 node, 1 exponential */
+#define MAGNUS_CF43 3   /* Section 2, Method Cf4:3: 3 Gauss nodes, 3 exponentials */
 
 /* Largest interpolation degree per substep the library plans for. */
 #define MAGNUS_MAX_DEGREE 64
@@ -69,7 +71,8 @@ typedef void* magnus_stream;   /* hipStream_t */
  *           row_ptr[dim] = nnz), col_idx[nnz] (0 <= col < dim), val[nnz]
  *           complex128.  Section 3 fixes CSR as the sparse format.
  *           MAGNUS_DENSE: val is a row-major dim x dim complex128 matrix with
- *           row stride ld >= dim elements (element (i, j) at val[i*ld + j]);
+ *           row stride ld >= dim elements (element (i, j) at val[i*ld + j]),
+ *           the same ld for H1 and H2;
  *           row_ptr, col_idx, nnz unused.
  *   lam_min, lam_max  an enclosure of the term's spectrum (Section 3: the Leja
  *           method needs an estimate of the spectrum).  Fill them with
@@ -141,10 +144,28 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
 /* Reserve (once) a dim x dim complex128 device buffer in the context for the
  * assembled exponent H_hat = a H1 + b H2 of dense terms.  With it, groups of
  * states that share the field run one MFMA GEMM per Leja iteration instead of
- * two (Section 4 assembles H(t) on the device likewise).  An explicit
- * allocation entry point: calls made without it work, at twice the flops.
+ * two, and a single state whose exponential needs at least 4 iterations
+ * assembles H_hat once (48 dim^2 bytes) and then reads one matrix per
+ * iteration instead of two (Section 4 assembles H(t) on the device likewise).
+ * An explicit allocation entry point: calls made without it work, reading
+ * both terms in every iteration.
  * Errors: EINVAL (dim < 1), EHIP (allocation failure). */
 int magnus_reserve_dense(magnus_ctx* ctx, int64_t dim);
+
+/* Assemble the commutator K = i [H1, H2] of two dense terms in the context
+ * (Section 2, Method M4; Section 4 forms the commutator of the M4 exponent
+ * with matrix products): one complex GEMM C = H1 H2 on the FP64 matrix cores,
+ * then K = i (C - C^H), since H2 H1 = (H1 H2)^H for Hermitian terms.  Sets
+ * h->k_min, h->k_max from K's Gershgorin discs (tighter than the
+ * 2 |H1| |H2| of magnus_spectral_bounds).  Needed before M4 steps or
+ * commutator exponents (kappa != 0) on dense terms, which then assemble
+ * H1 + b H2 + kappa K once per exponential.  The context keeps K (it
+ * allocates dim^2 complex128 for it, and reserves the magnus_reserve_dense
+ * buffer) for this pair of terms, recognised by their value pointers, dim
+ * and ld; a later call for another pair replaces it.  Synchronous.
+ * Errors: EINVAL (null or non-dense terms), EDOMAIN, ENOMEM (dim above
+ * max_dim), EHIP. */
+int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
 
 /* Free the workspace and the context (NULL is accepted). */
 int magnus_destroy(magnus_ctx* ctx);
@@ -196,10 +217,14 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
                    const void* psi_in, void* psi_out, int32_t batch, const magnus_leja_opts* opts,
                    magnus_stats* stats, magnus_stream stream);
 
-/* nsteps steps of `method` (MAGNUS_CF4 or MAGNUS_M4) in place on psi
- * (batch*dim complex128, device) on the grid t_n = t0 + n tau (the one-step
- * scheme of Section 2 repeated; control flow stays on the host, Section 3).
- *   f_nodes     HOST double[batch_f][nsteps][2]: f(t_n + c1 tau), f(t_n + c2 tau).
+/* nsteps steps of `method` in place on psi (batch*dim complex128, device) on
+ * the grid t_n = t0 + n tau (the one-step scheme of Section 2 repeated;
+ * control flow stays on the host, Section 3).  Methods: MAGNUS_CF4, MAGNUS_M4,
+ * MAGNUS_M2 (exp(tau A(t_n + tau/2))), MAGNUS_CF43 (Method Cf4:3: three
+ * exponentials exp(tau sum_j alpha_ij A_j) on the three Gauss nodes
+ * c = 1/2 -+ sqrt(15)/10, 1/2, the factor of the last row acting first).
+ *   f_nodes     HOST double[batch_f][nsteps][q]: f(t_n + c_j tau), j < q, with
+ *               q = magnus_method_nodes(method) (2, 2, 1, 3).
  *   batch_f     1 (one field for all states) or batch (one field per state).
  *   checkpoints NULL, or DEVICE storage for ceil(nsteps/every_k)+1 copies of psi:
  *               slot j receives psi after j*every_k steps (slot 0 = psi0), and
@@ -210,6 +235,26 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
               int64_t nsteps, const double* f_nodes, int32_t batch_f, void* psi, int32_t batch,
               void* checkpoints, int32_t every_k, const magnus_leja_opts* opts,
               magnus_stats* stats, magnus_stream stream);
+
+/* One problem of a ragged batch: its own Hamiltonian, states and fields. */
+typedef struct {
+  magnus_hamiltonian h;   /* spectral enclosures filled */
+  void* psi;              /* DEVICE, batch * h.H1.dim complex128, propagated in place */
+  int32_t batch;          /* states of this problem */
+  int32_t batch_f;        /* 1 or batch */
+  const double* f_nodes;  /* HOST [batch_f][nsteps][q], q = magnus_method_nodes(method) */
+} magnus_problem;
+
+/* nsteps steps of `method` for several independent problems of different
+ * sizes (the one-step scheme of Section 2 on each).  CSR problems of the
+ * product-of-exponentials methods (Cf4, Cf4:3, M2) whose dimension is at most
+ * 4096 all run in one persistent launch (one workgroup per state carries
+ * every step with its vectors in LDS); the others run as batched
+ * propagations.  Tolerances as in propagate (tol_mode 1: budget over the
+ * exponentials of each state).  Errors as propagate. */
+int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_t nprob, int32_t method,
+                            double tau, int64_t nsteps, const magnus_leja_opts* opts, magnus_stats* stats,
+                            magnus_stream stream);
 
 /* ---- adjoint (gradient of a final-state fidelity) ------------------------------ */
 
@@ -235,7 +280,7 @@ int64_t magnus_adjoint_workspace_bytes(int64_t dim, int64_t nsteps, int32_t ever
  *   workspace DEVICE scratch of at least magnus_adjoint_workspace_bytes bytes,
  *             caller-owned.
  *   loss      HOST double; grad HOST double[P].
- * H1, H2 must be CSR and the context needs max_batch >= 2.  Synchronous.
+ * CSR or dense terms; the context needs max_batch >= 2.  Synchronous.
  * Errors: EINVAL, EDOMAIN, ENOMEM (workspace or context too small), ENOCONV, EHIP, ENAN. */
 int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, int64_t nsteps,
                              const double* f_nodes, const double* df_nodes, int32_t nparams, const void* psi0,
@@ -252,6 +297,7 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
 #define MAGNUS_KERNEL_DENSE_LEJA 3  /* two-term dense Leja iteration */
 #define MAGNUS_KERNEL_CSR_MULTI  4  /* two-term CSR Leja iteration on a group of states */
 #define MAGNUS_KERNEL_DENSE_MFMA 5  /* dense group Leja iteration (FP64 MFMA GEMM) */
+#define MAGNUS_KERNEL_PERSIST    6  /* whole small-state propagations, one workgroup per state */
 
 /* enable = 1: from now on bracket every iteration kernel the context launches
  * with a pair of HIP events on the call's stream (previous records are
@@ -265,8 +311,13 @@ int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t*
 
 /* ---- host planning helpers (pure host code, no device needed) ------------------- */
 
-/* t_out[2n + j] = t0 + n tau + c_{j+1} tau for n < nsteps, j in {0, 1}: the two
- * Gauss nodes shared by Methods M4 and Cf4 (Section 2). */
+/* Field samples per step of `method` (Section 2): 2 for Cf4 and M4 (two
+ * Gauss nodes), 1 for M2 (midpoint), 3 for Cf4:3 (three Gauss nodes);
+ * EINVAL for an unknown method. */
+int magnus_method_nodes(int32_t method);
+
+/* t_out[q n + j] = t0 + n tau + c_j tau for n < nsteps, j < q: the quadrature
+ * nodes of `method` (Section 2), q = magnus_method_nodes(method). */
 int magnus_quadrature_nodes(int32_t method, double t0, double tau, int64_t nsteps, double* t_out);
 
 /* The first m+1 Leja points of [-2, 2]: xi_0 = 2, then each point maximises

@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libmagnus.so")
 
 OK, EINVAL, EDOMAIN, ENOCONV, EHIP, ENOMEM, ENAN = 0, -1, -2, -3, -4, -5, -6
 CSR, DENSE = 0, 1
-CF4, M4 = 0, 1
+CF4, M4, M2, CF43 = 0, 1, 2, 3
 MAX_DEGREE = 64
-METHODS = {"CF4": CF4, "M4": M4}
+METHODS = {"CF4": CF4, "M4": M4, "M2": M2, "CF43": CF43}
 
 
 class MagnusError(RuntimeError):
@@ -37,6 +37,11 @@ class Term(C.Structure):
 
 class Hamiltonian(C.Structure):
     _fields_ = [("H1", Term), ("H2", Term), ("k_min", C.c_double), ("k_max", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("h", Hamiltonian), ("psi", C.c_void_p), ("batch", C.c_int32), ("batch_f", C.c_int32),
+                ("f_nodes", C.POINTER(C.c_double))]
 
 
 class LejaOpts(C.Structure):
@@ -60,7 +65,9 @@ EXPORTS = ("magnus_create", "magnus_destroy", "magnus_last_error", "magnus_check
            "expmv_leja", "magnus_step_cf4", "magnus_step_m4", "propagate", "magnus_quadrature_nodes",
            "magnus_leja_points", "magnus_divided_differences", "magnus_leja_error", "magnus_leja_plan",
            "magnus_timing", "magnus_timing_read", "magnus_reserve_dense", "magnus_adjoint_workspace_bytes",
-           "magnus_propagate_adjoint")
+           "magnus_propagate_adjoint", "magnus_propagate_ragged", "magnus_method_nodes",
+           "magnus_dense_commutator")
+KERNEL_PERSIST = 6
 KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA, KERNEL_CSR_MULTI, KERNEL_DENSE_MFMA = 0, 1, 2, 3, 4, 5
 
 
@@ -86,6 +93,7 @@ def lib():
         "propagate": (C.c_int, [vp, P(Hamiltonian), i32, dbl, i64, P(dbl), i32, vp, i32, vp, i32, P(LejaOpts),
                                 P(Stats), vp]),
         "magnus_quadrature_nodes": (C.c_int, [i32, dbl, dbl, i64, P(dbl)]),
+        "magnus_method_nodes": (C.c_int, [i32]),
         "magnus_leja_points": (C.c_int, [i32, P(dbl)]),
         "magnus_divided_differences": (C.c_int, [dbl, i32, P(dbl)]),
         "magnus_leja_error": (dbl, [dbl, i32]),
@@ -93,7 +101,9 @@ def lib():
         "magnus_timing": (C.c_int, [vp, i32]),
         "magnus_timing_read": (C.c_int, [vp, i32, P(dbl), P(i64)]),
         "magnus_reserve_dense": (C.c_int, [vp, i64]),
+        "magnus_dense_commutator": (C.c_int, [vp, P(Hamiltonian), vp]),
         "magnus_adjoint_workspace_bytes": (i64, [i64, i64, i32]),
+        "magnus_propagate_ragged": (C.c_int, [vp, P(Problem), i32, i32, dbl, i64, P(LejaOpts), P(Stats), vp]),
         "magnus_propagate_adjoint": (C.c_int, [vp, P(Hamiltonian), dbl, i64, P(dbl), P(dbl), i32, vp, vp, i32, vp,
                                                i64, P(dbl), P(dbl), P(LejaOpts), P(Stats), vp]),
     }
@@ -117,10 +127,17 @@ def _dptr(a: np.ndarray):
 # ---------------------------------------------------------------------------
 # Host planning helpers
 # ---------------------------------------------------------------------------
+def magnus_method_nodes(method: int) -> int:
+    q = lib().magnus_method_nodes(method)
+    _check(q if q < 0 else OK)
+    return q
+
+
 def magnus_quadrature_nodes(method: int, t0: float, tau: float, nsteps: int) -> np.ndarray:
-    out = np.zeros(2 * nsteps, dtype=np.float64)
+    q = magnus_method_nodes(method)
+    out = np.zeros(q * nsteps, dtype=np.float64)
     _check(lib().magnus_quadrature_nodes(method, t0, tau, nsteps, _dptr(out)))
-    return out.reshape(nsteps, 2)
+    return out.reshape(nsteps, q)
 
 
 def magnus_leja_points(m: int) -> np.ndarray:
@@ -228,13 +245,16 @@ class DeviceHamiltonian:
 
     @staticmethod
     def from_dense(H1, H2, device: str = "cuda") -> "DeviceHamiltonian":
-        """H1, H2: row-major complex128 arrays (numpy or torch) of shape (dim, dim)."""
+        """H1, H2: row-major complex128 arrays (numpy or torch) of shape (dim, dim); a device
+        tensor whose rows are contiguous but padded (row stride > dim) is used as it is."""
         torch = _torch()
         ts = []
         terms = []
         for H in (H1, H2):
             t = H if isinstance(H, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(H))
-            t = t.to(device=device, dtype=torch.complex128).contiguous()
+            t = t.to(device=device, dtype=torch.complex128)
+            if t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+                t = t.contiguous()
             ts.append(t)
             n = t.shape[0]
             terms.append(Term(DENSE, 0, n, 0, t.stride(0), None, None, t.data_ptr(), 0.0, 0.0))
@@ -244,6 +264,12 @@ class DeviceHamiltonian:
 
 def magnus_spectral_bounds(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:
     _check(lib().magnus_spectral_bounds(ctx.handle, C.byref(ham.struct), _stream()))
+    return ham
+
+
+def magnus_dense_commutator(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:
+    """Assemble K = i[H1, H2] of dense terms in the context (needed for M4 on dense terms)."""
+    _check(lib().magnus_dense_commutator(ctx.handle, C.byref(ham.struct), _stream()))
     return ham
 
 
@@ -306,17 +332,19 @@ def magnus_step_m4(ctx, ham, tau, f1, f2, psi_in, psi_out=None, opts=None, stats
 
 def propagate(ctx: Context, ham: DeviceHamiltonian, method: int, tau: float, f_nodes, psi, checkpoints=None,
               every_k: int = 1, opts: LejaOpts | None = None, stats: bool = False):
-    """nsteps = len(f_nodes) steps in place on psi.  f_nodes: (nsteps, 2) or (batch, nsteps, 2) host array."""
+    """nsteps = len(f_nodes) steps in place on psi.  f_nodes: (nsteps, q) or (batch, nsteps, q) host
+    array of the field at the method's q quadrature nodes (magnus_quadrature_nodes)."""
     batch = _states(psi, ham.dim)
     f = np.ascontiguousarray(f_nodes, dtype=np.float64)
+    q = magnus_method_nodes(method)
     if f.ndim == 2:
         batch_f, nsteps = 1, f.shape[0]
     elif f.ndim == 3:
         batch_f, nsteps = f.shape[0], f.shape[1]
     else:
-        raise ValueError("f_nodes must be (nsteps, 2) or (batch, nsteps, 2)")
-    if f.shape[-1] != 2:
-        raise ValueError("f_nodes last axis must hold the two Gauss-node samples")
+        raise ValueError(f"f_nodes must be (nsteps, {q}) or (batch, nsteps, {q})")
+    if f.shape[-1] != q:
+        raise ValueError(f"f_nodes last axis must hold the method's {q} node samples")
     ck = None
     if checkpoints is not None:
         _states(checkpoints.reshape(-1, ham.dim), ham.dim)
@@ -365,3 +393,32 @@ def magnus_propagate_adjoint(ctx: Context, ham: DeviceHamiltonian, tau: float, f
     s = _finish(rc, st, stats)
     out = (loss.value, grad[:P].copy())
     return (out + (s,)) if stats else out
+
+
+def magnus_propagate_ragged(ctx: Context, problems, method: int, tau: float, opts: LejaOpts | None = None,
+                            stats: bool = False):
+    """problems: list of (DeviceHamiltonian, psi, f_nodes) with psi (batch, dim) or (dim,) device
+    states propagated in place and f_nodes (nsteps, q) or (batch, nsteps, q)."""
+    arr = (Problem * len(problems))()
+    keep = []
+    nsteps = None
+    q = magnus_method_nodes(method)
+    for i, (ham, psi, f_nodes) in enumerate(problems):
+        batch = _states(psi, ham.dim)
+        f = np.ascontiguousarray(f_nodes, dtype=np.float64)
+        if f.shape[-1] != q:
+            raise ValueError(f"problem {i}: f_nodes last axis must hold the method's {q} node samples")
+        batch_f = 1 if f.ndim == 2 else f.shape[0]
+        ns = f.shape[-2]
+        if nsteps is None:
+            nsteps = ns
+        elif ns != nsteps:
+            raise ValueError("all problems need the same number of steps")
+        keep.append(f)
+        arr[i] = Problem(ham.struct, psi.data_ptr(), batch, batch_f, _dptr(f))
+    st = Stats()
+    o = opts or leja_opts()
+    rc = lib().magnus_propagate_ragged(ctx.handle, arr, len(problems), method, tau, nsteps, C.byref(o),
+                                       C.byref(st) if stats else None, _stream())
+    del keep
+    return _finish(rc, st, stats)

@@ -27,6 +27,9 @@ using magnus::CsrDev;
 using magnus::ExpPlan;
 using magnus::IterArgs;
 using magnus::MultiArgs;
+using magnus::PersistArgs;
+using magnus::PersistExp;
+using magnus::PersistProblem;
 using magnus::Slot;
 
 namespace {
@@ -54,6 +57,10 @@ enum Vec { kA = 0, kB, kS0, kS1, kS2, kU, kV, kY, kNumVec };
 
 // Device table of per-state Leja parameters (ColParam entries) filled once per call segment.
 constexpr size_t kTableCap = 1 << 18;
+// Per-call headers of the persistent small-state kernel.
+constexpr size_t kArenaBytes = 8u << 20;
+// States of at most this many entries run whole propagations in one workgroup.
+constexpr int64_t kSmallDim = magnus::kPersistMaxDim;
 
 }  // namespace
 
@@ -65,8 +72,15 @@ struct magnus_ctx {
   Slot* slots = nullptr;       // one control block per state of a batch
   int nslots = 0;
   ColParam* table = nullptr;   // kTableCap entries
+  unsigned char* arena = nullptr;  // kArenaBytes
+  int persist = 1;                 // MAGNUS_PERSIST=0 disables the small-state kernel
   double2* assembled = nullptr;  // magnus_reserve_dense
   int64_t assembled_dim = 0;
+  double2* comm = nullptr;       // magnus_dense_commutator: K = i[H1, H2], row stride comm_dim
+  int64_t comm_dim = 0;
+  const void* comm_h1 = nullptr;  // the dense pair K belongs to (value pointers, dim, ld)
+  const void* comm_h2 = nullptr;
+  int64_t comm_n = 0, comm_ld = 0;
   double* partials = nullptr;  // npartials doubles
   size_t npartials = 0;
   int64_t max_grid = 0;
@@ -75,7 +89,8 @@ struct magnus_ctx {
   std::set<std::tuple<const void*, const void*, const void*, int64_t, int64_t>> validated;
   std::mutex mu;
   // kernel timing: (kind, start, stop) per recorded launch, events reused from a pool
-  int csr_variant = 0;  // 0 auto, 1 nonzero-streaming, 2 row-per-lane (MAGNUS_CSR_VARIANT)
+  int csr_variant = 0;  // MAGNUS_CSR_VARIANT: 0 auto (wave tiles of 8 rows from 65536 rows on),
+                        // 1 nonzero-streaming, 2-4 row-per-lane (64/32/128 rows), 5-6 wave tiles (8/16 rows)
   bool timing = false;
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;
   std::vector<hipEvent_t> pool;
@@ -116,6 +131,8 @@ int check_ham(magnus_ctx* ctx, const magnus_hamiltonian* h, int need_k) {
   rc = check_term(h->H2, dim, "H2");
   if (rc) return rc;
   if (h->H1.format != h->H2.format) return fail(MAGNUS_EINVAL, "H1 and H2 must share a format");
+  if (h->H1.format == MAGNUS_DENSE && h->H1.ld != h->H2.ld)
+    return fail(MAGNUS_EINVAL, "dense H1 and H2 must share the row stride ld");
   if (need_k && (!is_fin(h->k_min) || !is_fin(h->k_max) || h->k_min > h->k_max))
     return fail(MAGNUS_EDOMAIN, "commutator enclosure [%g, %g] invalid", h->k_min, h->k_max);
   return MAGNUS_OK;
@@ -194,6 +211,7 @@ int dense_scan(magnus_ctx* ctx, const magnus_term& t, hipStream_t s, double* lo,
 // Host-side record of the work a call enqueued.
 struct Acc {
   int64_t exponentials = 0, substeps = 0, planned = 0;
+  int64_t extra_iters = 0;  // iterations already counted by nested calls
   int32_t max_m = 0, max_s = 0;
   double max_bound = 0.0;
   int products_per_iter = 2;
@@ -202,7 +220,14 @@ struct Acc {
 struct ExpOp {
   const magnus_hamiltonian* h;
   double a, b, kappa;
+  const double2* assembled = nullptr;  // dense: the exponent assembled (row stride dim), used with a = 1
 };
+
+// Whether the context holds K = i[H1, H2] of this pair of dense terms.
+bool dense_comm_ready(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  return ctx->comm && ctx->comm_h1 == h->H1.val && ctx->comm_h2 == h->H2.val && ctx->comm_n == h->H1.dim &&
+         ctx->comm_ld == h->H1.ld;
+}
 
 int rows_per_block(magnus_ctx* ctx, int64_t dim) {
   if (ctx->csr_variant == 1) return dim >= 65536 ? 64 : 16;
@@ -211,7 +236,7 @@ int rows_per_block(magnus_ctx* ctx, int64_t dim) {
   if (ctx->csr_variant == 4) return -128;
   if (ctx->csr_variant == 5) return magnus::kWaveTile + 8;
   if (ctx->csr_variant == 6) return magnus::kWaveTile + 16;
-  return dim >= 65536 ? magnus::kRowLane : 16;
+  return dim >= 65536 ? magnus::kWaveTile + 8 : 16;
 }
 
 hipEvent_t next_event(magnus_ctx* ctx) {
@@ -261,10 +286,11 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
   a.wout = wout;
   a.pacc = pacc;
   if (h->H1.format == MAGNUS_DENSE) {
-    if (op.kappa != 0.0) return fail(MAGNUS_EINVAL, "commutator exponents need CSR terms");
+    if (op.kappa != 0.0) return fail(MAGNUS_EINVAL, "dense commutator exponents run assembled");
     a.x1 = win;
     a.x2 = win;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_LEJA, s, [&] {
+      if (op.assembled) return magnus::launch_dense2_iter(op.assembled, nullptr, dim, dim, a, s);
       return magnus::launch_dense2_iter(reinterpret_cast<const double2*>(h->H1.val),
                                         reinterpret_cast<const double2*>(h->H2.val), dim, h->H1.ld, a, s);
     }));
@@ -319,6 +345,20 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
                 o->max_degree, o->max_substeps, tol_e, 0.5 * std::fabs(tau) * 0.5 * (hi - lo));
   const int m = P.lp.m, ns = P.lp.s;
   const double tol_sub = tol_e / (2.0 * ns);
+  // Dense terms: assemble the exponent once (48 dim^2 bytes) when that is
+  // cheaper than reading both terms in every iteration (16 dim^2 bytes more
+  // each), and always for a commutator exponent (K itself is assembled).
+  ExpOp it = op;
+  if (op.h->H1.format == MAGNUS_DENSE && (op.kappa != 0.0 || (ctx->assembled_dim >= dim && m * ns >= 4))) {
+    if (op.kappa != 0.0 && !dense_comm_ready(ctx, op.h))
+      return fail(MAGNUS_EINVAL, "dense commutator exponents need magnus_dense_commutator for this pair of terms");
+    if (ctx->assembled_dim < dim) return fail(MAGNUS_ENOMEM, "no assembly buffer (magnus_reserve_dense)");
+    HIP_TRY(magnus::launch_dense_assemble(reinterpret_cast<const double2*>(op.h->H1.val),
+                                          reinterpret_cast<const double2*>(op.h->H2.val), op.h->H1.ld, (int)dim,
+                                          op.a, op.b, op.kappa != 0.0 ? ctx->comm : nullptr, op.kappa,
+                                          ctx->assembled, s));
+    it = ExpOp{op.h, 1.0, 0.0, 0.0, ctx->assembled};
+  }
   const double2* cur = src;
   for (int sub = 0; sub < ns; ++sub) {
     const bool last = (sub == ns - 1);
@@ -328,7 +368,7 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
     for (int i = 1; i <= m; ++i) {
       const double2* win = (i == 1) ? cur : ((i - 1) % 2 == 1 ? ctx->vec(kA) : ctx->vec(kB));
       double2* wout = (i % 2 == 1) ? ctx->vec(kA) : ctx->vec(kB);
-      int rc = launch_iteration(ctx, op, P, i, win, wout, Pbuf, tol_sub, o->early_termination, s);
+      int rc = launch_iteration(ctx, it, P, i, win, wout, Pbuf, tol_sub, o->early_termination, s);
       if (rc) return rc;
     }
     cur = Pbuf;
@@ -372,8 +412,8 @@ int end_call(magnus_ctx* ctx, const Acc& acc, double tol_e, magnus_stats* st, hi
   st->exponentials = acc.exponentials;
   st->substeps = acc.substeps;
   st->planned_iters = acc.planned;
-  st->iters = iters;
-  st->hv_products = iters * acc.products_per_iter;
+  st->iters = iters + acc.extra_iters;
+  st->hv_products = st->iters * acc.products_per_iter;
   st->max_degree_used = acc.max_m;
   st->max_substeps_used = acc.max_s;
   st->max_err_bound = acc.max_bound;
@@ -387,16 +427,27 @@ double per_exp_tol(const magnus_leja_opts* o, int64_t exps_per_state) {
   return o->tol;
 }
 
-// One step of Method Cf4 on one state: the right factor exp(tau(alpha2 A1 + alpha1 A2)) first.
-int cf4_state(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1, double f2,
-              const double2* in, double2* out, double tol_e, const magnus_leja_opts* o, Acc* acc,
-              hipStream_t s) {
-  const double beta = magnus::kAlpha2 * f1 + magnus::kAlpha1 * f2;
-  const double gamma = magnus::kAlpha1 * f1 + magnus::kAlpha2 * f2;
-  double2* mid = ctx->vec(kS2);
-  int rc = run_exponential(ctx, ExpOp{h, 0.5, beta, 0.0}, tau, in, mid, tol_e, o, acc, s);
-  if (rc) return rc;
-  return run_exponential(ctx, ExpOp{h, 0.5, gamma, 0.0}, tau, mid, out, tol_e, o, acc, s);
+// H2 coefficient of exponential k of a product-of-exponentials step.
+double scheme_b(const magnus::Scheme& S, int k, const double* f) {
+  double b = 0.0;
+  for (int j = 0; j < S.q; ++j) b += S.w[k][j] * f[j];
+  return b;
+}
+
+// One step of a product-of-exponentials method (Cf4, Cf4:3, M2) on one state,
+// f = the step's field samples; the factors act in the order of the scheme
+// (for Cf4 the right factor exp(tau(alpha2 A1 + alpha1 A2)) first).
+int cf_state(magnus_ctx* ctx, const magnus_hamiltonian* h, const magnus::Scheme& S, double tau, const double* f,
+             const double2* in, double2* out, double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  double2* mids[2] = {ctx->vec(kS2), ctx->vec(kU)};
+  const double2* src = in;
+  for (int k = 0; k < S.nexp; ++k) {
+    double2* dst = (k == S.nexp - 1) ? out : mids[k & 1];
+    int rc = run_exponential(ctx, ExpOp{h, S.rho[k], scheme_b(S, k, f), 0.0}, tau, src, dst, tol_e, o, acc, s);
+    if (rc) return rc;
+    src = dst;
+  }
+  return MAGNUS_OK;
 }
 
 // One step of Method M4 on one state: exp(-i tau (H1 + fbar H2 + kappa K)).
@@ -475,8 +526,8 @@ int plan_multi(const magnus_hamiltonian* h, const double* acoef, const double* b
       c.coup = frechet ? p.scale : 0.0;
       table->push_back(c);
     }
-  acc->exponentials += 1;
-  acc->substeps += s;
+  acc->exponentials += B;
+  acc->substeps += (int64_t)s * B;
   acc->planned += (int64_t)m * s * B;
   acc->max_m = std::max(acc->max_m, m);
   acc->max_s = std::max(acc->max_s, s);
@@ -500,13 +551,14 @@ int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E
   CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
   CsrDev t2{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
   const bool dense = h->H1.format == MAGNUS_DENSE;
-  const int grid = dense ? magnus::dense_mfma_row_blocks(dim) : magnus::csr2_multi_grid(dim, B);
+  const int grid = dense ? (E.frechet ? magnus::dense_frechet_grid(dim) : magnus::dense_mfma_row_blocks(dim))
+                         : magnus::csr2_multi_grid(dim, B);
   const int mode = E.frechet ? magnus::kMultiFrechet : magnus::kMultiLeja;
   const double2* D1 = reinterpret_cast<const double2*>(h->H1.val);
   const double2* D2 = reinterpret_cast<const double2*>(h->H2.val);
   long long ldd = h->H1.ld;
   if (dense && E.dense_terms == 1) {
-    HIP_TRY(magnus::launch_dense_assemble(D1, D2, h->H1.ld, dim, E.ca, E.cb, ctx->assembled, s));
+    HIP_TRY(magnus::launch_dense_assemble(D1, D2, h->H1.ld, dim, E.ca, E.cb, nullptr, 0.0, ctx->assembled, s));
     D1 = ctx->assembled;
     ldd = dim;
   }
@@ -531,7 +583,10 @@ int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E
       a.early = early;
       a.tol = tol_sub;
       a.joint = E.frechet;
-      if (dense)
+      if (dense && E.frechet)
+        HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_LEJA, s,
+                      [&] { return magnus::launch_dense_frechet(D1, D2, dim, h->H1.ld, a, s); }));
+      else if (dense)
         HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_MFMA, s,
                       [&] { return magnus::launch_dense_mfma(E.dense_terms, D1, D2, ldd, dim, a, s); }));
       else
@@ -594,14 +649,15 @@ int multi_expmv_group(magnus_ctx* ctx, const magnus_hamiltonian* h, int B, const
   return MAGNUS_OK;
 }
 
-// Cf4 steps for a group of B states held interleaved in kY, f values per
-// state: fn(c, n, j) = f(t_n + c_j tau) of state c.
+// Product-of-exponentials steps for a group of B states held interleaved in
+// kY, f values per state: fn(c, n, j) = f(t_n + c_j tau) of state c.
 template <class F>
-int multi_cf4_steps(magnus_ctx* ctx, const magnus_hamiltonian* h, int B, double tau, int64_t n0, int64_t n1,
-                    F fn, double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+int multi_cf_steps(magnus_ctx* ctx, const magnus_hamiltonian* h, const magnus::Scheme& S, int B, double tau,
+                   int64_t n0, int64_t n1, F fn, double tol_e, const magnus_leja_opts* o, Acc* acc,
+                   hipStream_t s) {
   double2* Y = ctx->vec(kY);
-  double2* M = ctx->vec(kS2);
-  std::vector<double> av(B, 0.5), bb(B), bg(B);
+  double2* mids[2] = {ctx->vec(kS2), ctx->vec(kU)};
+  std::vector<double> av(B), bv(B), fv(S.q);
   // steps are planned and uploaded in segments that fit the parameter table
   int64_t n = n0;
   while (n < n1) {
@@ -609,36 +665,160 @@ int multi_cf4_steps(magnus_ctx* ctx, const magnus_hamiltonian* h, int B, double 
     std::vector<MultiExp> exps;
     int64_t k = n;
     for (; k < n1; ++k) {
-      for (int c = 0; c < B; ++c) {
-        const double f1 = fn(c, k, 0), f2 = fn(c, k, 1);
-        bb[c] = magnus::kAlpha2 * f1 + magnus::kAlpha1 * f2;
-        bg[c] = magnus::kAlpha1 * f1 + magnus::kAlpha2 * f2;
-      }
       const size_t mark = table.size();
-      MultiExp Eb, Ea;
       Acc trial = *acc;
-      int rc = plan_group(ctx, h, av.data(), bb.data(), B, tau, tol_e, o, &table, &Eb, &trial);
-      if (rc) return rc;
-      rc = plan_group(ctx, h, av.data(), bg.data(), B, tau, tol_e, o, &table, &Ea, &trial);
-      if (rc) return rc;
+      std::vector<MultiExp> step(S.nexp);
+      const double2* src = Y;
+      for (int e = 0; e < S.nexp; ++e) {
+        for (int c = 0; c < B; ++c) {
+          for (int j = 0; j < S.q; ++j) fv[j] = fn(c, k, j);
+          av[c] = S.rho[e];
+          bv[c] = scheme_b(S, e, fv.data());
+        }
+        int rc = plan_group(ctx, h, av.data(), bv.data(), B, tau, tol_e, o, &table, &step[e], &trial);
+        if (rc) return rc;
+        step[e].src = src;
+        step[e].dst = (e == S.nexp - 1) ? Y : mids[e & 1];
+        src = step[e].dst;
+      }
       if (table.size() > kTableCap) {
         if (k == n) return fail(MAGNUS_ENOMEM, "one step needs more than the parameter table holds");
         table.resize(mark);
         break;
       }
       *acc = trial;
-      Eb.src = Y;
-      Eb.dst = M;
-      Ea.src = M;
-      Ea.dst = Y;
-      exps.push_back(Eb);
-      exps.push_back(Ea);
+      for (const MultiExp& E : step) exps.push_back(E);
     }
     int rc = upload_table(ctx, table, s);
     if (rc) return rc;
     for (const MultiExp& E : exps)
       if ((rc = launch_multi(ctx, h, E, tol_e, o->early_termination, s))) return rc;
     n = k;
+  }
+  return MAGNUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Whole Cf4 propagations of small states, one workgroup per state.
+// ---------------------------------------------------------------------------
+struct SmallState {
+  int prob;
+  double2* psi;
+  const double* fn;  // this state's field samples, [nsteps][q]
+};
+
+bool small_ok(magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  return ctx->persist && h->H1.format == MAGNUS_CSR && h->H1.dim <= kSmallDim;
+}
+
+// Steps n0..n1-1 of every state in one launch.
+int persist_segment(magnus_ctx* ctx, const std::vector<const magnus_hamiltonian*>& hs,
+                    const std::vector<SmallState>& st, const magnus::Scheme& S, double tau, int64_t n0, int64_t n1,
+                    double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  const int nst = (int)st.size();
+  const int nexp = (int)(S.nexp * (n1 - n0));
+  if (nst > ctx->nslots) return fail(MAGNUS_ENOMEM, "%d small states exceed %d control slots", nst, ctx->nslots);
+  int64_t maxdim = 1;
+  for (auto* h : hs) maxdim = std::max<int64_t>(maxdim, h->H1.dim);
+  if (maxdim > magnus::kPersistMaxDim) return fail(MAGNUS_EINVAL, "dimension %lld too large for the small-state kernel", (long long)maxdim);
+  std::vector<ColParam> table;
+  std::vector<PersistExp> exps((size_t)nst * nexp);
+  const auto& xi = magnus::leja_points();
+  for (int b = 0; b < nst; ++b) {
+    const magnus_hamiltonian* h = hs[st[b].prob];
+    for (int64_t n = n0; n < n1; ++n) {
+      const double* f = st[b].fn + S.q * n;
+      for (int half = 0; half < S.nexp; ++half) {
+        const double rho = S.rho[half], coef = scheme_b(S, half, f);
+        double lo, hi;
+        magnus::weyl_interval(rho, h->H1.lam_min, h->H1.lam_max, coef, h->H2.lam_min, h->H2.lam_max, 0.0, 0.0, 0.0,
+                              &lo, &hi);
+        ExpPlan P;
+        if (!magnus::plan_exponential(tau, lo, hi, tol_e, o->max_degree, o->max_substeps, &P))
+          return fail(MAGNUS_ENOCONV, "no degree <= %d with <= %d substeps reaches tol %g", o->max_degree,
+                      o->max_substeps, tol_e);
+        PersistExp& E = exps[(size_t)b * nexp + S.nexp * (n - n0) + half];
+        E.m = P.lp.m;
+        E.s = P.lp.s;
+        E.table_off = (long long)table.size();
+        E.tol_sub = tol_e / (2.0 * P.lp.s);
+        for (int i = 1; i <= P.lp.m; ++i) {
+          ColParam c{};
+          c.a1 = P.scale * rho;
+          c.a2 = P.scale * coef;
+          c.sigma = P.scale * P.c + xi[i - 1];
+          c.dre = P.d[i].real();
+          c.dim = P.d[i].imag();
+          c.dabs = std::abs(P.d[i]);
+          c.d0re = P.d[0].real();
+          c.d0im = P.d[0].imag();
+          c.d0abs = std::abs(P.d[0]);
+          table.push_back(c);
+        }
+        acc->exponentials += 1;
+        acc->substeps += P.lp.s;
+        acc->planned += (int64_t)P.lp.m * P.lp.s;
+        acc->max_m = std::max(acc->max_m, P.lp.m);
+        acc->max_s = std::max(acc->max_s, P.lp.s);
+        acc->max_bound = std::max(acc->max_bound, P.lp.bound);
+      }
+    }
+  }
+  if (table.size() > kTableCap) return fail(MAGNUS_ENOMEM, "parameter table overflow");
+  // headers: problems | state_prob | state pointers | exponentials
+  std::vector<PersistProblem> probs(hs.size());
+  for (size_t i = 0; i < hs.size(); ++i) {
+    const magnus_hamiltonian* h = hs[i];
+    probs[i].t1 = CsrDev{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
+    probs[i].t2 = CsrDev{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
+    probs[i].dim = (int)h->H1.dim;
+  }
+  std::vector<int> sp(nst);
+  std::vector<double2*> ptrs(nst);
+  for (int b = 0; b < nst; ++b) {
+    sp[b] = st[b].prob;
+    ptrs[b] = st[b].psi;
+  }
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_prob = 0;
+  const size_t o_sp = align(o_prob + sizeof(PersistProblem) * probs.size());
+  const size_t o_ptr = align(o_sp + sizeof(int) * sp.size());
+  const size_t o_exp = align(o_ptr + sizeof(double2*) * ptrs.size());
+  const size_t total = o_exp + sizeof(PersistExp) * exps.size();
+  if (total > kArenaBytes) return fail(MAGNUS_ENOMEM, "call headers of %zu bytes exceed the arena", total);
+  std::vector<unsigned char> host(total);
+  memcpy(host.data() + o_prob, probs.data(), sizeof(PersistProblem) * probs.size());
+  memcpy(host.data() + o_sp, sp.data(), sizeof(int) * sp.size());
+  memcpy(host.data() + o_ptr, ptrs.data(), sizeof(double2*) * ptrs.size());
+  memcpy(host.data() + o_exp, exps.data(), sizeof(PersistExp) * exps.size());
+  HIP_TRY(hipMemcpyAsync(ctx->arena, host.data(), total, hipMemcpyHostToDevice, s));
+  int rc = upload_table(ctx, table, s);
+  if (rc) return rc;
+  PersistArgs a{};
+  a.probs = reinterpret_cast<const PersistProblem*>(ctx->arena + o_prob);
+  a.state_prob = reinterpret_cast<const int*>(ctx->arena + o_sp);
+  a.state = reinterpret_cast<double2* const*>(ctx->arena + o_ptr);
+  a.table = ctx->table;
+  a.exps = reinterpret_cast<const PersistExp*>(ctx->arena + o_exp);
+  a.nexp = nexp;
+  a.slots = ctx->slots;
+  a.early = o->early_termination;
+  HIP_TRY(timed(ctx, MAGNUS_KERNEL_PERSIST, s, [&] { return magnus::launch_persist_propagate(a, nst, (int)maxdim, s); }));
+  return MAGNUS_OK;
+}
+
+// All steps of a set of small-state problems, split into segments whose
+// tables fit (and at the given stop points).
+int persist_steps(magnus_ctx* ctx, const std::vector<const magnus_hamiltonian*>& hs,
+                  const std::vector<SmallState>& st, const magnus::Scheme& S, double tau, int64_t n0, int64_t n1,
+                  double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  const int64_t per_step = (int64_t)st.size() * S.nexp * std::max(1, o->max_degree) * 2;
+  int64_t L = std::max<int64_t>(1, (int64_t)kTableCap / std::max<int64_t>(per_step, 1));
+  L = std::min<int64_t>(L, (int64_t)(kArenaBytes / 2) / ((int64_t)sizeof(PersistExp) * S.nexp * (int64_t)st.size() + 1));
+  L = std::max<int64_t>(L, 1);
+  for (int64_t n = n0; n < n1; n += L) {
+    int rc = persist_segment(ctx, hs, st, S, tau, n, std::min(n1, n + L), tol_e, o, acc, s);
+    if (rc) return rc;
   }
   return MAGNUS_OK;
 }
@@ -671,11 +851,13 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   if (const char* v = getenv("MAGNUS_CSR_VARIANT")) c->csr_variant = atoi(v);
   c->max_grid = max_dim / 8 + 2;  // the smallest row block of any iteration kernel is 8 rows
   c->scan_len = 2 * (max_dim / 4 + 2) + 3 * (max_dim / 256 + 2);
-  c->nslots = std::max<int>(2, max_batch);
+  c->nslots = std::max<int>(256, max_batch);
+  if (const char* v = getenv("MAGNUS_PERSIST")) c->persist = atoi(v);
   const size_t nvec = (size_t)kNumVec * (size_t)max_dim * (size_t)max_batch;
   hipError_t e = hipMalloc(&c->vecs, sizeof(double2) * nvec);
   if (e == hipSuccess) e = hipMalloc(&c->slots, sizeof(Slot) * c->nslots);
   if (e == hipSuccess) e = hipMalloc(&c->table, sizeof(ColParam) * kTableCap);
+  if (e == hipSuccess) e = hipMalloc(&c->arena, kArenaBytes);
   c->npartials = 2 * (size_t)c->max_grid + (size_t)max_dim * (size_t)std::max(1, max_batch) / 8 + (size_t)max_dim + 64;
   if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->npartials);
   if (e == hipSuccess) e = hipMalloc(&c->scan, sizeof(double) * (size_t)c->scan_len);
@@ -707,13 +889,55 @@ int magnus_reserve_dense(magnus_ctx* ctx, int64_t dim) {
   return MAGNUS_OK;
 }
 
+int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream) {
+  if (!ctx || !h) return fail(MAGNUS_EINVAL, "null argument");
+  int rc = check_ham(ctx, h, 0);
+  if (rc) return rc;
+  if (h->H1.format != MAGNUS_DENSE) return fail(MAGNUS_EINVAL, "magnus_dense_commutator needs dense terms");
+  const int64_t dim = h->H1.dim;
+  if ((rc = magnus_reserve_dense(ctx, dim))) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->comm_dim < dim) {
+    if (ctx->comm) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(ctx->comm));
+      ctx->comm = nullptr;
+      ctx->comm_dim = 0;
+    }
+    HIP_TRY(hipMalloc(&ctx->comm, sizeof(double2) * (size_t)dim * (size_t)dim));
+    ctx->comm_dim = dim;
+  }
+  ctx->comm_h1 = ctx->comm_h2 = nullptr;
+  const double2* H1 = reinterpret_cast<const double2*>(h->H1.val);
+  const double2* H2 = reinterpret_cast<const double2*>(h->H2.val);
+  HIP_TRY(magnus::launch_zgemm(H1, h->H1.ld, H2, h->H2.ld, ctx->assembled, (int)dim, s));
+  HIP_TRY(magnus::launch_commutator_combine(ctx->assembled, (int)dim, ctx->comm, s));
+  magnus_term kt{};
+  kt.format = MAGNUS_DENSE;
+  kt.dim = dim;
+  kt.ld = dim;
+  kt.val = ctx->comm;
+  double lo, hi;
+  if ((rc = dense_scan(ctx, kt, s, &lo, &hi))) return rc;
+  h->k_min = lo;
+  h->k_max = hi;
+  ctx->comm_h1 = h->H1.val;
+  ctx->comm_h2 = h->H2.val;
+  ctx->comm_n = dim;
+  ctx->comm_ld = h->H1.ld;
+  return MAGNUS_OK;
+}
+
 int magnus_destroy(magnus_ctx* ctx) {
   if (!ctx) return MAGNUS_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->vecs) (void)hipFree(ctx->vecs);
   if (ctx->slots) (void)hipFree(ctx->slots);
   if (ctx->table) (void)hipFree(ctx->table);
+  if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->assembled) (void)hipFree(ctx->assembled);
+  if (ctx->comm) (void)hipFree(ctx->comm);
   if (ctx->partials) (void)hipFree(ctx->partials);
   if (ctx->scan) (void)hipFree(ctx->scan);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -771,7 +995,8 @@ int expmv_leja(magnus_ctx* ctx, const magnus_hamiltonian* h, double a, double b,
   if (!v || !w) return fail(MAGNUS_EINVAL, "null state pointer");
   if (!is_fin(a) || !is_fin(b) || !is_fin(kappa) || !is_fin(tau))
     return fail(MAGNUS_EDOMAIN, "non-finite coefficient or step");
-  if (kappa != 0.0 && h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "commutator exponents need CSR terms");
+  if (kappa != 0.0 && h->H1.format != MAGNUS_CSR && !dense_comm_ready(ctx, h))
+    return fail(MAGNUS_EINVAL, "dense commutator exponents need magnus_dense_commutator for this pair of terms");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = begin_call(ctx, s))) return rc;
   if ((rc = ensure_valid(ctx, h, s))) return rc;
@@ -803,27 +1028,30 @@ static int step_common(int method, magnus_ctx* ctx, const magnus_hamiltonian* h,
   if ((rc = check_opts(opts)) || (rc = check_batch(ctx, batch))) return rc;
   if (!psi_in || !psi_out) return fail(MAGNUS_EINVAL, "null state pointer");
   if (!is_fin(tau) || !is_fin(f1) || !is_fin(f2)) return fail(MAGNUS_EDOMAIN, "non-finite step or field value");
-  if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "M4 needs CSR terms");
+  if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR && !dense_comm_ready(ctx, h))
+    return fail(MAGNUS_EINVAL, "M4 on dense terms needs magnus_dense_commutator for this pair of terms");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = begin_call(ctx, s))) return rc;
   if ((rc = ensure_valid(ctx, h, s))) return rc;
   const int64_t dim = h->H1.dim;
-  const double tol_e = per_exp_tol(opts, method == MAGNUS_CF4 ? 2 : 1);
+  magnus::Scheme S;
+  magnus::method_scheme(method, &S);
+  const double fv[2] = {f1, f2};
+  const double tol_e = per_exp_tol(opts, S.nexp);
   Acc acc;
   acc.products_per_iter = method == MAGNUS_M4 ? 4 : 2;
   const double2* in = reinterpret_cast<const double2*>(psi_in);
   double2* out = reinterpret_cast<double2*>(psi_out);
   for (int32_t c = 0; c < batch;) {
-    const int g = (method == MAGNUS_CF4 && multi_ok(h, 0.0)) ? group_for(h, batch - c) : 1;
+    const int g = (!S.commutator && multi_ok(h, 0.0)) ? group_for(h, batch - c) : 1;
     if (g > 1) {
       HIP_TRY(magnus::launch_pack(in + c * dim, ctx->vec(kY), (int)dim, g, s));
-      rc = multi_cf4_steps(ctx, h, g, tau, 0, 1, [&](int, int64_t, int j) { return j == 0 ? f1 : f2; }, tol_e, opts,
-                           &acc, s);
+      rc = multi_cf_steps(ctx, h, S, g, tau, 0, 1, [&](int, int64_t, int j) { return fv[j]; }, tol_e, opts, &acc, s);
       if (rc) return rc;
       HIP_TRY(magnus::launch_unpack(ctx->vec(kY), out + c * dim, (int)dim, g, s));
     } else {
-      rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s)
-                                  : m4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s);
+      rc = S.commutator ? m4_state(ctx, h, tau, f1, f2, in + c * dim, out + c * dim, tol_e, opts, &acc, s)
+                        : cf_state(ctx, h, S, tau, fv, in + c * dim, out + c * dim, tol_e, opts, &acc, s);
     }
     if (rc) return rc;
     c += g;
@@ -846,7 +1074,8 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
 int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, double tau, int64_t nsteps,
               const double* f_nodes, int32_t batch_f, void* psi, int32_t batch, void* checkpoints,
               int32_t every_k, const magnus_leja_opts* opts, magnus_stats* stats, magnus_stream stream) {
-  if (method != MAGNUS_CF4 && method != MAGNUS_M4) return fail(MAGNUS_EINVAL, "unknown method %d", method);
+  magnus::Scheme S;
+  if (!magnus::method_scheme(method, &S)) return fail(MAGNUS_EINVAL, "unknown method %d", method);
   int rc = check_ham(ctx, h, method == MAGNUS_M4);
   if (rc) return rc;
   if ((rc = check_opts(opts)) || (rc = check_batch(ctx, batch))) return rc;
@@ -856,14 +1085,15 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
   if (batch_f != 1 && batch_f != batch) return fail(MAGNUS_EINVAL, "batch_f %d must be 1 or batch", batch_f);
   if (checkpoints && every_k < 1) return fail(MAGNUS_EINVAL, "every_k %d < 1", every_k);
   if (!is_fin(tau)) return fail(MAGNUS_EDOMAIN, "non-finite step");
-  for (int64_t k = 0; k < 2 * nsteps * (int64_t)batch_f; ++k)
+  for (int64_t k = 0; k < S.q * nsteps * (int64_t)batch_f; ++k)
     if (!is_fin(f_nodes[k])) return fail(MAGNUS_EDOMAIN, "non-finite field value at node %lld", (long long)k);
-  if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "M4 needs CSR terms");
+  if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR && !dense_comm_ready(ctx, h))
+    return fail(MAGNUS_EINVAL, "M4 on dense terms needs magnus_dense_commutator for this pair of terms");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = begin_call(ctx, s))) return rc;
   if ((rc = ensure_valid(ctx, h, s))) return rc;
   const int64_t dim = h->H1.dim;
-  const int64_t exps = (method == MAGNUS_CF4 ? 2 : 1) * nsteps;
+  const int64_t exps = S.nexp * nsteps;
   const double tol_e = per_exp_tol(opts, exps);
   Acc acc;
   acc.products_per_iter = method == MAGNUS_M4 ? 4 : 2;
@@ -873,9 +1103,14 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
   const size_t stride = (size_t)dim * (size_t)batch;
   if (ck) HIP_TRY(hipMemcpyAsync(ck, st, sizeof(double2) * stride, hipMemcpyDeviceToDevice, s));
   auto fval = [&](int c, int64_t n, int j) {
-    return f_nodes[((batch_f == 1 ? 0 : (int64_t)c) * nsteps + n) * 2 + j];
+    return f_nodes[((batch_f == 1 ? 0 : (int64_t)c) * nsteps + n) * S.q + j];
   };
-  const bool grouped = method == MAGNUS_CF4 && multi_ok(h, 0.0) && batch > 1;
+  const bool grouped = !S.commutator && multi_ok(h, 0.0) && batch > 1;
+  const bool small = !S.commutator && small_ok(ctx, h);
+  std::vector<SmallState> sst;
+  if (small)
+    for (int32_t c = 0; c < batch; ++c)
+      sst.push_back(SmallState{0, st + c * dim, f_nodes + (batch_f == 1 ? 0 : (int64_t)c) * nsteps * S.q});
   // checkpoint steps: multiples of every_k and the last step
   auto next_stop = [&](int64_t n) {
     if (!ck) return nsteps;
@@ -885,19 +1120,25 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
   int64_t n = 0;
   while (n < nsteps) {
     const int64_t stop = next_stop(n);
-    for (int32_t c = 0; c < batch;) {
+    if (small) {
+      rc = persist_steps(ctx, {h}, sst, S, tau, n, stop, tol_e, opts, &acc, s);
+      if (rc) return rc;
+    }
+    for (int32_t c = small ? batch : 0; c < batch;) {
       const int g = grouped ? group_for(h, batch - c) : 1;
       if (g > 1) {
         HIP_TRY(magnus::launch_pack(st + c * dim, ctx->vec(kY), (int)dim, g, s));
-        rc = multi_cf4_steps(ctx, h, g, tau, n, stop,
-                             [&](int cc, int64_t k, int j) { return fval(c + cc, k, j); }, tol_e, opts, &acc, s);
+        rc = multi_cf_steps(ctx, h, S, g, tau, n, stop,
+                            [&](int cc, int64_t k, int j) { return fval(c + cc, k, j); }, tol_e, opts, &acc, s);
         if (rc) return rc;
         HIP_TRY(magnus::launch_unpack(ctx->vec(kY), st + c * dim, (int)dim, g, s));
       } else {
         for (int64_t k = n; k < stop; ++k) {
           double2* y = st + c * dim;
-          rc = (method == MAGNUS_CF4) ? cf4_state(ctx, h, tau, fval(c, k, 0), fval(c, k, 1), y, y, tol_e, opts, &acc, s)
-                                      : m4_state(ctx, h, tau, fval(c, k, 0), fval(c, k, 1), y, y, tol_e, opts, &acc, s);
+          double fv[3];
+          for (int j = 0; j < S.q; ++j) fv[j] = fval(c, k, j);
+          rc = S.commutator ? m4_state(ctx, h, tau, fv[0], fv[1], y, y, tol_e, opts, &acc, s)
+                            : cf_state(ctx, h, S, tau, fv, y, y, tol_e, opts, &acc, s);
           if (rc) return rc;
         }
       }
@@ -926,7 +1167,7 @@ int magnus_timing(magnus_ctx* ctx, int32_t enable) {
 
 int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches) {
   if (!ctx || !total_ms || !launches) return fail(MAGNUS_EINVAL, "null argument");
-  if (kind < MAGNUS_KERNEL_CSR_LEJA || kind > MAGNUS_KERNEL_DENSE_MFMA) return fail(MAGNUS_EINVAL, "kernel class %d", kind);
+  if (kind < MAGNUS_KERNEL_CSR_LEJA || kind > MAGNUS_KERNEL_PERSIST) return fail(MAGNUS_EINVAL, "kernel class %d", kind);
   HIP_TRY(hipSetDevice(ctx->device));
   double t = 0.0;
   int64_t n = 0;
@@ -941,6 +1182,72 @@ int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t*
   *total_ms = t;
   *launches = n;
   return MAGNUS_OK;
+}
+
+int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_t nprob, int32_t method,
+                            double tau, int64_t nsteps, const magnus_leja_opts* opts, magnus_stats* stats,
+                            magnus_stream stream) {
+  if (!ctx) return fail(MAGNUS_EINVAL, "null context");
+  if (!probs || nprob < 1) return fail(MAGNUS_EINVAL, "no problems");
+  magnus::Scheme S;
+  if (!magnus::method_scheme(method, &S)) return fail(MAGNUS_EINVAL, "unknown method %d", method);
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (nsteps < 0 || !is_fin(tau)) return fail(MAGNUS_EINVAL, "bad nsteps or tau");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = begin_call(ctx, s))) return rc;
+  for (int32_t i = 0; i < nprob; ++i) {
+    const magnus_problem& P = probs[i];
+    if ((rc = check_ham(ctx, &P.h, method == MAGNUS_M4))) return rc;
+    if (!P.psi || P.batch < 1 || (P.batch_f != 1 && P.batch_f != P.batch) || (nsteps > 0 && !P.f_nodes))
+      return fail(MAGNUS_EINVAL, "problem %d: bad state, batch or field", i);
+    for (int64_t k = 0; k < S.q * nsteps * (int64_t)P.batch_f; ++k)
+      if (!is_fin(P.f_nodes[k])) return fail(MAGNUS_EDOMAIN, "problem %d: non-finite field value", i);
+    if ((rc = ensure_valid(ctx, &P.h, s))) return rc;
+  }
+  const double tol_e = per_exp_tol(opts, S.nexp * nsteps);
+  Acc acc;
+  // small problems (product-of-exponentials methods): every state in one persistent launch
+  std::vector<const magnus_hamiltonian*> hs;
+  std::vector<SmallState> sst;
+  std::vector<int> big;
+  for (int32_t i = 0; i < nprob; ++i) {
+    const magnus_problem& P = probs[i];
+    if (!S.commutator && small_ok(ctx, &P.h)) {
+      const int pi = (int)hs.size();
+      hs.push_back(&P.h);
+      double2* psi = reinterpret_cast<double2*>(P.psi);
+      for (int32_t c = 0; c < P.batch; ++c)
+        sst.push_back(
+            SmallState{pi, psi + c * P.h.H1.dim, P.f_nodes + (P.batch_f == 1 ? 0 : (int64_t)c) * nsteps * S.q});
+    } else {
+      big.push_back(i);
+    }
+  }
+  // the large problems first: each is one batched propagation (which resets the control slots)
+  for (int i : big) {
+    const magnus_problem& P = probs[i];
+    if (P.batch > ctx->max_batch) return fail(MAGNUS_ENOMEM, "problem %d: batch %d exceeds max_batch", i, P.batch);
+    magnus_leja_opts o = *opts;
+    o.tol = tol_e;
+    o.tol_mode = 0;
+    magnus_stats ps{};
+    rc = propagate(ctx, &P.h, method, tau, nsteps, P.f_nodes, P.batch_f, P.psi, P.batch, nullptr, 1, &o,
+                   stats ? &ps : nullptr, stream);
+    if (rc) return rc;
+    acc.exponentials += ps.exponentials;
+    acc.substeps += ps.substeps;
+    acc.planned += ps.planned_iters;
+    acc.max_m = std::max(acc.max_m, ps.max_degree_used);
+    acc.max_s = std::max(acc.max_s, ps.max_substeps_used);
+    acc.max_bound = std::max(acc.max_bound, ps.max_err_bound);
+    if (stats) acc.extra_iters += ps.iters;  // counted by the nested call
+  }
+  if (!sst.empty() && nsteps > 0) {
+    if (!big.empty()) HIP_TRY(magnus::launch_slot_reset(ctx->slots, ctx->nslots, s));
+    if ((rc = persist_steps(ctx, hs, sst, S, tau, 0, nsteps, tol_e, opts, &acc, s))) return rc;
+  }
+  return end_call(ctx, acc, tol_e, stats, s);
 }
 
 int64_t magnus_adjoint_workspace_bytes(int64_t dim, int64_t nsteps, int32_t every_k) {
@@ -959,7 +1266,6 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
   int rc = check_ham(ctx, h, 0);
   if (rc) return rc;
   if ((rc = check_opts(opts))) return rc;
-  if (h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "the adjoint needs CSR terms");
   if (ctx->max_batch < 2) return fail(MAGNUS_ENOMEM, "the adjoint needs a context with max_batch >= 2");
   if (nsteps < 1 || nparams < 0 || every_k < 1) return fail(MAGNUS_EINVAL, "nsteps, nparams or every_k out of range");
   if (!f_nodes || (nparams > 0 && !df_nodes) || !psi0 || !psi_target || !workspace || !loss || (nparams > 0 && !grad))
@@ -998,8 +1304,10 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
   // forward sweep with checkpoints (state kept in mu)
   HIP_TRY(hipMemcpyAsync(ck, psi0, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(mu, psi0, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
+  magnus::Scheme cf4;
+  magnus::method_scheme(MAGNUS_CF4, &cf4);
   for (int64_t n = 0; n < nsteps; ++n) {
-    rc = cf4_state(ctx, h, tau, f_nodes[2 * n], f_nodes[2 * n + 1], mu, mu, tol_e, opts, &acc, s);
+    rc = cf_state(ctx, h, cf4, tau, f_nodes + 2 * n, mu, mu, tol_e, opts, &acc, s);
     if (rc) return rc;
     if ((n + 1) % k == 0 || n + 1 == nsteps) {
       const int64_t slot = (n + 1) % k == 0 ? (n + 1) / k : nck - 1;
@@ -1074,13 +1382,19 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
   return end_call(ctx, acc, tol_e, stats, s);
 }
 
+int magnus_method_nodes(int32_t method) {
+  magnus::Scheme S;
+  if (!magnus::method_scheme(method, &S)) return fail(MAGNUS_EINVAL, "unknown method %d", method);
+  return S.q;
+}
+
 int magnus_quadrature_nodes(int32_t method, double t0, double tau, int64_t nsteps, double* t_out) {
-  if (method != MAGNUS_CF4 && method != MAGNUS_M4) return fail(MAGNUS_EINVAL, "unknown method %d", method);
+  magnus::Scheme S;
+  if (!magnus::method_scheme(method, &S)) return fail(MAGNUS_EINVAL, "unknown method %d", method);
   if (nsteps < 0 || (nsteps > 0 && !t_out)) return fail(MAGNUS_EINVAL, "bad output");
   for (int64_t n = 0; n < nsteps; ++n) {
     const double tn = t0 + (double)n * tau;
-    t_out[2 * n] = tn + magnus::kC1 * tau;
-    t_out[2 * n + 1] = tn + magnus::kC2 * tau;
+    for (int j = 0; j < S.q; ++j) t_out[S.q * n + j] = tn + S.c[j] * tau;
   }
   return MAGNUS_OK;
 }

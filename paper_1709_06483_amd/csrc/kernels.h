@@ -82,7 +82,8 @@ hipError_t launch_dense_gershgorin(const double2* H, int dim, long long ld, doub
                                    hipStream_t s);
 int dense_gershgorin_grid(int dim);
 
-// Dense two-term Leja iteration (mode kLeja only).
+// Dense Leja iteration (mode kLeja only): two terms, or one (an assembled
+// exponent) when H2 is null.
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s);
 int dense2_grid(int dim);
@@ -142,14 +143,58 @@ hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, l
                              const MultiArgs& a, hipStream_t s);
 int dense_mfma_row_blocks(int dim);
 // out = ca H1 + cb H2 (dim x dim, row stride ld in, dim out).
+// out = ca H1 + cb H2 + ck K (H1, H2 with row stride ld; K, if not null, and
+// out with row stride dim).
 hipError_t launch_dense_assemble(const double2* H1, const double2* H2, long long ld, int dim, double ca, double cb,
-                                 double2* out, hipStream_t s);
+                                 const double2* K, double ck, double2* out, hipStream_t s);
+
+// C = A B (n x n complex128, row strides lda, ldb in, n out) on the FP64 matrix cores.
+hipError_t launch_zgemm(const double2* A, long long lda, const double2* B, long long ldb, double2* C, int n,
+                        hipStream_t s);
+// K = i (C - C^H), n x n with row stride n.
+hipError_t launch_commutator_combine(const double2* C, int n, double2* K, hipStream_t s);
+
+// Dense Frechet block iteration (B == 2 interleaved pair, joint stop test);
+// decide with dense_frechet_grid(dim) workgroups.
+hipError_t launch_dense_frechet(const double2* H1, const double2* H2, int dim, long long ld, const MultiArgs& a,
+                                hipStream_t s);
+int dense_frechet_grid(int dim);
 
 // out = sum_i conj(x[i*sx]) y[i*sy] (fixed order; partials: 1024 doubles).
 hipError_t launch_cdot(const double2* x, long long sx, const double2* y, long long sy, long long n, double* partials,
                        double2* out, hipStream_t s);
 // dst (interleaved pair) = [0; v].
 hipError_t launch_frechet_init(const double2* v, double2* dst, int dim, hipStream_t s);
+
+// ---- whole propagations in one workgroup per state (small dimensions) ----
+
+struct PersistProblem {
+  CsrDev t1, t2;
+  int dim;
+};
+
+// One exponential of one state: m iterations per substep, s substeps, the
+// parameters of iteration i at table[table_off + i - 1].
+struct PersistExp {
+  int m, s;
+  long long table_off;
+  double tol_sub;
+};
+
+struct PersistArgs {
+  const PersistProblem* probs;
+  const int* state_prob;   // problem of each state (workgroup)
+  double2* const* state;   // state vector of each workgroup (in place)
+  const ColParam* table;
+  const PersistExp* exps;  // nexp per state, state-major
+  int nexp;                // exponentials per state (even: Cf4 pairs)
+  Slot* slots;             // one per state
+  int early;
+};
+
+// Largest dimension of the one-workgroup-per-state kernel (two LDS vectors).
+constexpr int kPersistMaxDim = 4096;
+hipError_t launch_persist_propagate(const PersistArgs& a, int nstates, int max_dim, hipStream_t s);
 
 // Small helpers.
 hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_t s);

@@ -394,8 +394,11 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Seven waves per SIMD (at most 72 VGPRs): enough independent tiles in flight
+// per CU to cover the memory latency of each tile's load -> gather chain.  The
+// commutator pass holds two more own-row vectors and gets six (no spills).
 template <int RPW, int MODE>
-__global__ __launch_bounds__(kThreads) void csr2_wave_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+__global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
   constexpr int NWAVE = kThreads / 64;
   constexpr int G = 64 / RPW;      // entry groups per row
   constexpr int CAPW = RPW * 32;   // entries staged per chunk
@@ -405,7 +408,10 @@ __global__ __launch_bounds__(kThreads) void csr2_wave_kernel(CsrDev t1, CsrDev t
   __shared__ int scol[NWAVE][CAPW];
   __shared__ int srp[NWAVE][2][RPW + 1];
   __shared__ double wred[2][NWAVE];
-  if (a.check_stop && load_stopped(a.slot)) return;
+  // The stop flag is the same for every wave of the launch; it is tested only
+  // once the row pointers and own-row operands are in flight, so its latency
+  // overlaps theirs.
+  const int stopped = a.check_stop ? load_stopped(a.slot) : 0;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -416,11 +422,12 @@ __global__ __launch_bounds__(kThreads) void csr2_wave_kernel(CsrDev t1, CsrDev t
   const int row = row0 + r;
   double pw = 0.0, pv = 0.0;
 
+  int rpa = 0, rpb = 0;
+  d2 w_old = {0.0, 0.0}, p_old = {0.0, 0.0}, own1 = {0.0, 0.0}, own2 = {0.0, 0.0};
   if (nrows > 0) {
-    if (lane <= nrows) srp[wv][0][lane] = t1.rp[row0 + lane];
-    if (lane >= 32 && lane - 32 <= nrows) srp[wv][1][lane - 32] = t2.rp[row0 + lane - 32];
+    if (lane <= nrows) rpa = t1.rp[row0 + lane];
+    if (lane >= 32 && lane - 32 <= nrows) rpb = t2.rp[row0 + lane - 32];
     // own-row operands of the update, fetched early
-    d2 w_old = {0.0, 0.0}, p_old = {0.0, 0.0}, own1 = {0.0, 0.0}, own2 = {0.0, 0.0};
     if (owner) {
       if constexpr (MODE != kSplit) {
         w_old = tod2(a.wcur[row]);
@@ -431,6 +438,12 @@ __global__ __launch_bounds__(kThreads) void csr2_wave_kernel(CsrDev t1, CsrDev t
         own2 = tod2(a.x2[row]);
       }
     }
+  }
+  if (stopped) return;  // uniform over the workgroup
+
+  if (nrows > 0) {
+    if (lane <= nrows) srp[wv][0][lane] = rpa;
+    if (lane >= 32 && lane - 32 <= nrows) srp[wv][1][lane - 32] = rpb;
     wave_lds_sync();
     const int base1 = srp[wv][0][0], n1 = srp[wv][0][nrows] - base1;
     const int base2 = srp[wv][1][0], n2 = srp[wv][1][nrows] - base2;
@@ -543,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void csr2_wave_kernel(CsrDev t1, CsrDev t
 // transaction, and each gathered x_j is loaded once per lane for RPW rows and
 // both terms.
 // ---------------------------------------------------------------------------
-template <int RPW>
+template <int RPW, int NT>
 __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1, const double2* H2,
                                                               int dim, long long ld, IterArgs a) {
   if (a.check_stop && load_stopped(a.slot)) return;
@@ -566,7 +579,7 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
       if (r < nr) {
         const long long off = (long long)(rbase + r) * ld + j;
         acc1[r] += cmul(__builtin_nontemporal_load(A1 + off), xj);
-        acc2[r] += cmul(__builtin_nontemporal_load(A2 + off), xj);
+        if constexpr (NT == 2) acc2[r] += cmul(__builtin_nontemporal_load(A2 + off), xj);
       }
     }
   }
@@ -578,11 +591,13 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
     for (int off = 32; off > 0; off >>= 1) {
       s1.x += __shfl_xor(s1.x, off, 64);
       s1.y += __shfl_xor(s1.y, off, 64);
-      s2.x += __shfl_xor(s2.x, off, 64);
-      s2.y += __shfl_xor(s2.y, off, 64);
+      if constexpr (NT == 2) {
+        s2.x += __shfl_xor(s2.x, off, 64);
+        s2.y += __shfl_xor(s2.y, off, 64);
+      }
     }
     if (lane == r && r < nr) {
-      const d2 y = rmul(a.a1, s1) + rmul(a.a2, s2);
+      const d2 y = NT == 2 ? rmul(a.a1, s1) + rmul(a.a2, s2) : rmul(a.a1, s1);
       leja_row(a, rbase + r, y, pw, pv);
     }
   }
@@ -752,7 +767,8 @@ int dense2_grid(int dim) {
 
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s) {
-  dense2_iter_kernel<kDenseRPW><<<dense2_grid(dim), kThreads, 0, s>>>(H1, H2, dim, ld, a);
+  if (H2) dense2_iter_kernel<kDenseRPW, 2><<<dense2_grid(dim), kThreads, 0, s>>>(H1, H2, dim, ld, a);
+  else dense2_iter_kernel<kDenseRPW, 1><<<dense2_grid(dim), kThreads, 0, s>>>(H1, H1, dim, ld, a);
   return hipGetLastError();
 }
 

@@ -181,15 +181,19 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
   }
 }
 
-// H = a H1 + b H2 (row-major, row stride ld in, dim out).
+// H = a H1 + b H2 (+ k K) (row-major, row stride ld for H1, H2, dim for K and out).
+template <bool WITH_K>
 __global__ void dense_assemble_kernel(const double2* __restrict__ H1, const double2* __restrict__ H2, long long ld,
-                                      int dim, double ca, double cb, double2* __restrict__ out) {
+                                      int dim, double ca, double cb, const double2* __restrict__ K, double ck,
+                                      double2* __restrict__ out) {
   const long long n = (long long)dim * dim;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const long long r = i / dim, c = i % dim;
     const d2 x = __builtin_nontemporal_load(reinterpret_cast<const d2*>(H1) + r * ld + c);
     const d2 y = __builtin_nontemporal_load(reinterpret_cast<const d2*>(H2) + r * ld + c);
-    out[i] = fromd2(rmul(ca, x) + rmul(cb, y));
+    d2 h = rmul(ca, x) + rmul(cb, y);
+    if constexpr (WITH_K) h += rmul(ck, __builtin_nontemporal_load(reinterpret_cast<const d2*>(K) + i));
+    out[i] = fromd2(h);
   }
 }
 
@@ -207,8 +211,9 @@ hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, l
 }
 
 hipError_t launch_dense_assemble(const double2* H1, const double2* H2, long long ld, int dim, double ca, double cb,
-                                 double2* out, hipStream_t s) {
-  dense_assemble_kernel<<<4096, kThreads, 0, s>>>(H1, H2, ld, dim, ca, cb, out);
+                                 const double2* K, double ck, double2* out, hipStream_t s) {
+  if (K) dense_assemble_kernel<true><<<4096, kThreads, 0, s>>>(H1, H2, ld, dim, ca, cb, K, ck, out);
+  else dense_assemble_kernel<false><<<4096, kThreads, 0, s>>>(H1, H2, ld, dim, ca, cb, nullptr, 0.0, out);
   return hipGetLastError();
 }
 

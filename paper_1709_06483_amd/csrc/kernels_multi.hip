@@ -202,6 +202,92 @@ __global__ void unpack_kernel(const double2* __restrict__ src, double2* __restri
   }
 }
 
+// Dense block (Frechet) iteration on the interleaved pair (x, y) of the
+// block vector of [[H, H2], [0, H]], H = a1 H1 + a2 H2 (scaled): a wave owns
+// RPW rows, its lanes stride over the columns, so each matrix element is
+// loaded once (coalesced, non-temporal) for both x and y.
+template <int RPW>
+__global__ __launch_bounds__(kThreads) void dense_frechet_kernel(const double2* H1, const double2* H2, int dim,
+                                                                long long ld, MultiArgs a) {
+  __shared__ double wsum[kThreads / 64][2][2];
+  if (a.check_stop && load_stopped(&a.slots[0])) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int rbase = (L * (kThreads / 64) + wv) * RPW;
+  const int nr = max(0, min(RPW, dim - rbase));
+  const d2* X = reinterpret_cast<const d2*>(a.x);
+  const d2* A1 = reinterpret_cast<const d2*>(H1);
+  const d2* A2 = reinterpret_cast<const d2*>(H2);
+  d2 acc[RPW][4];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = d2{0.0, 0.0};
+  for (int j = lane; j < dim; j += 64) {
+    const d2 xj = X[2 * (long long)j], yj = X[2 * (long long)j + 1];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (r < nr) {
+        const long long off = (long long)(rbase + r) * ld + j;
+        const d2 h1 = __builtin_nontemporal_load(A1 + off), h2 = __builtin_nontemporal_load(A2 + off);
+        acc[r][0] += cmul(h1, xj);
+        acc[r][1] += cmul(h2, xj);
+        acc[r][2] += cmul(h1, yj);
+        acc[r][3] += cmul(h2, yj);
+      }
+    }
+  }
+  const ColParam P0 = a.prm[0], P1 = a.prm[1];
+  double pw[2] = {0.0, 0.0}, pv[2] = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        acc[r][q].x += __shfl_xor(acc[r][q].x, off, 64);
+        acc[r][q].y += __shfl_xor(acc[r][q].y, off, 64);
+      }
+    if (lane == r && r < nr) {
+      const long long row = rbase + r;
+      const d2 ys[2] = {rmul(P0.a1, acc[r][0]) + rmul(P0.a2, acc[r][1]) + rmul(P0.coup, acc[r][3]),
+                        rmul(P1.a1, acc[r][2]) + rmul(P1.a2, acc[r][3])};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const ColParam& P = c == 0 ? P0 : P1;
+        const long long idx = 2 * row + c;
+        const d2 w_old = X[idx];
+        const d2 wn = ys[c] - rmul(P.sigma, w_old);
+        const d2 dd = {P.dre, P.dim};
+        d2 p;
+        if (a.first) {
+          p = cmul(d2{P.d0re, P.d0im}, w_old) + cmul(dd, wn);
+          pv[c] += nrm2(w_old);
+        } else {
+          p = tod2(a.pacc[idx]) + cmul(dd, wn);
+        }
+        a.wout[idx] = fromd2(wn);
+        a.pacc[idx] = fromd2(p);
+        pw[c] += nrm2(wn);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    pw[c] = wave_sum(pw[c]);
+    pv[c] = wave_sum(pv[c]);
+  }
+  if (lane == 0)
+    for (int c = 0; c < 2; ++c) { wsum[wv][c][0] = pw[c]; wsum[wv][c][1] = pv[c]; }
+  __syncthreads();
+  if (tid < 2) {
+    double bw = 0.0, bv = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) { bw += wsum[w][tid][0]; bv += wsum[w][tid][1]; }
+    a.partials[((long long)blockIdx.x * 2 + tid) * 2] = bw;
+    a.partials[((long long)blockIdx.x * 2 + tid) * 2 + 1] = bv;
+  }
+}
+
 // Fixed-order complex dot product sum_i conj(x_i) y_i (strided operands).
 constexpr int kDotBlocks = 512;
 __global__ __launch_bounds__(kThreads) void cdot_partial_kernel(const double2* x, long long sx, const double2* y,
@@ -297,6 +383,19 @@ hipError_t launch_csr2_multi(int mode, const CsrDev& t1, const CsrDev& t2, int d
 
 hipError_t launch_multi_decide(const MultiArgs& a, int grid, hipStream_t s) {
   multi_decide_kernel<<<a.joint ? 1 : a.B, kDecideThreads, 0, s>>>(a, grid);
+  return hipGetLastError();
+}
+
+constexpr int kFrechetRPW = 2;
+int dense_frechet_grid(int dim) {
+  const int rows = kFrechetRPW * (kThreads / 64);
+  return (dim + rows - 1) / rows;
+}
+
+hipError_t launch_dense_frechet(const double2* H1, const double2* H2, int dim, long long ld, const MultiArgs& a,
+                                hipStream_t s) {
+  if (a.B != 2) return hipErrorInvalidValue;
+  dense_frechet_kernel<kFrechetRPW><<<dense_frechet_grid(dim), kThreads, 0, s>>>(H1, H2, dim, ld, a);
   return hipGetLastError();
 }
 

@@ -349,4 +349,62 @@ bool plan_exponential(double tau, double lo, double hi, double tol, int max_degr
   return true;
 }
 
+bool method_scheme(int method, Scheme* out) {
+  Scheme S;
+  switch (method) {
+    case 0: {  // Cf4: exp(tau(a1 A1 + a2 A2)) exp(tau(a2 A1 + a1 A2)), the second factor acting first
+      S.q = 2;
+      S.nexp = 2;
+      S.c[0] = kC1;
+      S.c[1] = kC2;
+      S.rho[0] = S.rho[1] = 0.5;
+      S.w[0][0] = kAlpha2;
+      S.w[0][1] = kAlpha1;
+      S.w[1][0] = kAlpha1;
+      S.w[1][1] = kAlpha2;
+      break;
+    }
+    case 1: {  // M4: one exponential with the averaged field and the commutator
+      S.q = 2;
+      S.nexp = 1;
+      S.commutator = true;
+      S.c[0] = kC1;
+      S.c[1] = kC2;
+      S.rho[0] = 1.0;
+      S.w[0][0] = S.w[0][1] = 0.5;
+      break;
+    }
+    case 2: {  // M2: exponential midpoint rule
+      S.q = 1;
+      S.nexp = 1;
+      S.c[0] = 0.5;
+      S.rho[0] = 1.0;
+      S.w[0][0] = 1.0;
+      break;
+    }
+    case 3: {  // Cf4:3 on the three Gauss nodes; rows of the printed alpha matrix, last row first
+      const double r15 = 3.8729833462074168852;  // sqrt(15)
+      const double p = 37.0 / 240.0, q = 10.0 * r15 / 261.0;
+      const double rows[3][3] = {{p - q, -1.0 / 30.0, p + q},
+                                 {-11.0 / 360.0, 23.0 / 45.0, -11.0 / 360.0},
+                                 {p + q, -1.0 / 30.0, p - q}};
+      S.q = 3;
+      S.nexp = 3;
+      S.c[0] = 0.5 - r15 / 10.0;
+      S.c[1] = 0.5;
+      S.c[2] = 0.5 + r15 / 10.0;
+      for (int k = 0; k < 3; ++k) {
+        const double* row = rows[2 - k];
+        S.rho[k] = row[0] + row[1] + row[2];  // A_j = -i(H1 + f_j H2)
+        for (int j = 0; j < 3; ++j) S.w[k][j] = row[j];
+      }
+      break;
+    }
+    default:
+      return false;
+  }
+  *out = S;
+  return true;
+}
+
 }  // namespace magnus

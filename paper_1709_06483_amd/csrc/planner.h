@@ -94,4 +94,22 @@ constexpr double kC2 = 0.5 + kSqrt3 / 6.0;
 constexpr double kAlpha1 = (3.0 - 2.0 * kSqrt3) / 12.0;
 constexpr double kAlpha2 = (3.0 + 2.0 * kSqrt3) / 12.0;
 
+// One step of a Magnus-type method for H(t) = H1 + f(t) H2, from the samples
+// f_j = f(t_n + c_j tau), j < q.  Commutator-free methods (Cf4, Cf4:3) and
+// the exponential midpoint rule (M2) are products of exponentials
+// exp(-i tau (rho_k H1 + b_k H2)) with b_k = sum_j w[k][j] f_j, listed in the
+// order they act on the state (the rightmost factor of Section 2 first).
+// M4 has one exponential with the commutator term (commutator = true).
+struct Scheme {
+  int q = 0;
+  int nexp = 0;
+  bool commutator = false;
+  double c[3] = {0, 0, 0};
+  double rho[3] = {0, 0, 0};
+  double w[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+};
+
+// Method ids as in the public header: 0 Cf4, 1 M4, 2 M2, 3 Cf4:3.
+bool method_scheme(int method, Scheme* out);
+
 }  // namespace magnus

@@ -83,3 +83,24 @@ def test_adjoint_argument_errors():
                                     B._ptr(prob.psi_target), 4, B._ptr(small), 16, B.C.byref(B.C.c_double()),
                                     B._dptr(np.zeros(4)), B.C.byref(B.leja_opts()), None, None)
     assert rc == B.ENOMEM
+
+
+def test_dense_gradient_matches_oracle():
+    """Dense power-law H0 + f(t) V (dim 200) with a 12-mode Fourier field."""
+    N, P, T, nsteps = 200, 12, 2.0, 40
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=20)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=21)
+    ctx = B.Context(max_dim=N, max_batch=2)
+    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H0, V))
+    theta = inputs.fourier_theta(P, 40)
+    tau = T / nsteps
+    psi0 = inputs.random_states(N, seed=41)
+    tgt = inputs.random_states(N, seed=42)
+    prob = A.ControlProblem.with_basis(ctx, ham, tau, nsteps, inputs.fourier_basis(P, T),
+                                       torch.from_numpy(psi0).cuda(), torch.from_numpy(tgt).cuda(), every_k=8,
+                                       opts=B.leja_opts(1e-13))
+    loss, grad = prob.loss_and_grad(theta)
+    f = prob.basis_nodes @ theta
+    L_ref, g_ref, _ = oa.loss_and_gradient(H0, V, tau, f, prob.basis_nodes, psi0, tgt)
+    assert abs(loss - L_ref) <= 1e-11
+    assert np.max(np.abs(grad - g_ref)) <= 1e-9 * max(1.0, np.max(np.abs(g_ref)))

@@ -1,0 +1,112 @@
+"""Method M4 on dense terms (Section 2): the commutator K = i[H1, H2] assembled
+once by the FP64-MFMA GEMM, then one assembled exponent H1 + fbar H2 + kappa K
+per step; and the single-state assembled-exponent path for dense Cf4."""
+import numpy as np
+import pytest
+
+from oracle import magnus as mg
+from paper_1709_06483_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected only where a GPU exists
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1709_06483_amd import binding as B  # noqa: E402
+
+BUDGET = 1e-10
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def nodes(method, f, tau, nsteps):
+    return np.vectorize(f)(B.magnus_quadrature_nodes(B.METHODS[method], 0.0, tau, nsteps))
+
+
+@pytest.mark.parametrize("N,pad", [(200, 0), (130, 7)])
+def test_dense_m4_matches_oracle(N, pad):
+    """Power-law dense terms (dim 200, and dim 130 stored with row stride 137):
+    the commutator's enclosure holds its spectrum and 25 M4 steps match the oracle."""
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=60)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=61)
+    c = B.Context(max_dim=N, max_batch=1)
+    if pad:
+        P0 = torch.zeros((N, N + pad), dtype=torch.complex128, device="cuda")
+        P1 = torch.zeros((N, N + pad), dtype=torch.complex128, device="cuda")
+        P0[:, :N] = dev(H0)
+        P1[:, :N] = dev(V)
+        ham = B.DeviceHamiltonian.from_dense(P0[:, :N], P1[:, :N])
+        assert ham.struct.H1.ld == N + pad
+    else:
+        ham = B.DeviceHamiltonian.from_dense(H0, V)
+    ham = B.magnus_spectral_bounds(c, ham)
+    psi0 = inputs.random_states(N, seed=62)
+    tau, nsteps = 0.01, 25
+    f = inputs.sin_field(1.0, 2.0)
+    fn = nodes("M4", f, tau, nsteps)
+    with pytest.raises(B.MagnusError) as e:
+        B.propagate(c, ham, B.M4, tau, fn, dev(psi0))
+    assert e.value.code == B.EINVAL
+    B.magnus_dense_commutator(c, ham)
+    K = 1j * (H0 @ V - V @ H0)
+    lam = np.linalg.eigvalsh(K)
+    assert ham.struct.k_min <= lam[0] and lam[-1] <= ham.struct.k_max
+    assert ham.struct.k_max <= 2 * np.abs(K).sum(axis=1).max()
+    psi = dev(psi0)
+    _, st = B.propagate(c, ham, B.M4, tau, fn, psi, opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    ref = mg.propagate("M4", mg.two_term(H0, V, f), tau, nsteps, psi0, expm="eig")
+    assert rel(host(psi), ref) <= BUDGET
+    assert st["exponentials"] == nsteps
+    # one step through the step entry point
+    t1, t2 = B.magnus_quadrature_nodes(B.M4, 0.0, tau, 1)[0]
+    out = B.magnus_step_m4(c, ham, tau, f(t1), f(t2), dev(psi0), opts=B.leja_opts(1e-12))
+    ref1 = mg.propagate("M4", mg.two_term(H0, V, f), tau, 1, psi0, expm="eig")
+    assert rel(host(out), ref1) <= 4e-11
+    c.close()
+
+
+def test_dense_commutator_belongs_to_its_pair():
+    """K is kept for one pair of terms: M4 on another pair is refused until it is assembled."""
+    N = 96
+    A = [inputs.powerlaw_hermitian(N, 1.5, seed=70 + k) for k in range(3)]
+    c = B.Context(max_dim=N, max_batch=1)
+    h1 = B.magnus_dense_commutator(c, B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(A[0], A[1])))
+    h2 = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(A[0], A[2]))
+    psi0 = inputs.random_states(N, seed=73)
+    B.magnus_step_m4(c, h1, 0.01, 0.3, 0.7, dev(psi0))
+    h2.struct.k_min, h2.struct.k_max = h1.struct.k_min, h1.struct.k_max
+    with pytest.raises(B.MagnusError):
+        B.magnus_step_m4(c, h2, 0.01, 0.3, 0.7, dev(psi0))
+    c.close()
+
+
+def test_dense_single_state_assembled_cf4():
+    """With the assembly buffer reserved, a single dense state assembles each exponent
+    (when it needs at least 4 iterations) and reads one matrix per iteration."""
+    N, tau, nsteps = 300, 0.02, 12
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=80)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=81)
+    c = B.Context(max_dim=N, max_batch=1)
+    c.reserve_dense(N)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(H0, V))
+    f = inputs.sin_field(1.0)
+    psi0 = inputs.random_states(N, seed=82)
+    psi = dev(psi0)
+    _, st = B.propagate(c, ham, B.CF4, tau, nodes("CF4", f, tau, nsteps), psi,
+                        opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    assert st["max_degree_used"] >= 4
+    ref = mg.propagate("CF4", mg.two_term(H0, V, f), tau, nsteps, psi0, expm="eig")
+    assert rel(host(psi), ref) <= BUDGET
+    c.close()

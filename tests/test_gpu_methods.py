@@ -1,0 +1,129 @@
+"""GPU parity of the other product-of-exponentials methods of Section 2: the
+exponential midpoint rule M2 and Method Cf4:3 (three exponentials on three Gauss
+nodes), on every execution path (one-workgroup-per-state kernel, per-iteration
+launches, grouped multi-state CSR kernel, dense MFMA groups, ragged batches),
+against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import magnus as mg
+from paper_1709_06483_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected only where a GPU exists
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1709_06483_amd import binding as B  # noqa: E402
+
+BUDGET = 1e-10
+NEXP = {"M2": 1, "CF43": 3}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def nodes(method, f, tau, nsteps):
+    return np.vectorize(f)(B.magnus_quadrature_nodes(B.METHODS[method], 0.0, tau, nsteps))
+
+
+@pytest.mark.parametrize("persist", ["1", "0"])
+@pytest.mark.parametrize("method", ["M2", "CF43"])
+def test_chain_n10_single_state(method, persist, monkeypatch):
+    """n = 10 chain, cos(2t) field, 60 steps of 0.01: the small-state kernel (persist 1)
+    and per-iteration launches (persist 0) both match the oracle."""
+    monkeypatch.setenv("MAGNUS_PERSIST", persist)
+    H1, H2 = inputs.chain_terms(10)
+    c = B.Context(max_dim=1024, max_batch=1)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    tau, nsteps = 0.01, 60
+    f = inputs.cos_field(2.0)
+    psi0 = inputs.random_states(1024, seed=500)
+    psi = dev(psi0)
+    _, st = B.propagate(c, ham, B.METHODS[method], tau, nodes(method, f, tau, nsteps), psi,
+                        opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    ref = mg.propagate(method, mg.two_term(H1.to_scipy(), H2.to_scipy(), f), tau, nsteps, psi0, expm="taylor")
+    assert rel(host(psi), ref) <= BUDGET
+    assert st["exponentials"] == NEXP[method] * nsteps
+    c.close()
+
+
+@pytest.mark.parametrize("method", ["M2", "CF43"])
+def test_grouped_csr_states_per_state_fields(method):
+    """n = 13 chain (dim 8192, above the small-state limit), 5 states with their own
+    field amplitudes: a group of 4 through the multi-state kernel and one alone."""
+    H1, H2 = inputs.chain_terms(13)
+    c = B.Context(max_dim=1 << 13, max_batch=5)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    tau, nsteps = 0.01, 8
+    fields = [inputs.cos_field(2.0, 1.0 + k / 4) for k in range(5)]
+    fn = np.stack([nodes(method, f, tau, nsteps) for f in fields])
+    psi0 = inputs.random_states(1 << 13, seed=501, batch=5)
+    psi = dev(psi0)
+    B.propagate(c, ham, B.METHODS[method], tau, fn, psi, opts=B.leja_opts(BUDGET, tol_mode=1))
+    out = host(psi)
+    for k in (0, 3, 4):
+        P = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[k])
+        ref = mg.propagate(method, P, tau, nsteps, psi0[k], expm="taylor")
+        assert rel(out[k], ref) <= BUDGET, k
+    c.close()
+
+
+@pytest.mark.parametrize("method", ["M2", "CF43"])
+def test_dense_single_and_group(method):
+    """Dense power-law terms, dim 200: one state (GEMV iteration) and a group of 6
+    (FP64 MFMA GEMM iteration)."""
+    N, tau, nsteps = 200, 0.005, 10
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=40)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=41)
+    c = B.Context(max_dim=N, max_batch=6)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(H0, V))
+    f = inputs.sin_field(1.0)
+    fn = nodes(method, f, tau, nsteps)
+    psi0 = inputs.random_states(N, seed=502, batch=6)
+    one = dev(psi0[0])
+    B.propagate(c, ham, B.METHODS[method], tau, fn, one, opts=B.leja_opts(BUDGET, tol_mode=1))
+    grp = dev(psi0)
+    B.propagate(c, ham, B.METHODS[method], tau, fn, grp, opts=B.leja_opts(BUDGET, tol_mode=1))
+    out = host(grp)
+    P = mg.two_term(H0, V, f)
+    for k in (0, 5):
+        ref = mg.propagate(method, P, tau, nsteps, psi0[k], expm="eig")
+        assert rel(out[k], ref) <= BUDGET, k
+    assert rel(host(one), mg.propagate(method, P, tau, nsteps, psi0[0], expm="eig")) <= BUDGET
+    c.close()
+
+
+def test_ragged_cf43():
+    """Cf4:3 on chains of 8 and 12 spins (one persistent launch) and 13 spins (batched)."""
+    tau, nsteps = 0.01, 10
+    c = B.Context(max_dim=1 << 13, max_batch=2)
+    probs, refs = [], []
+    for n, per in ((8, 2), (12, 1), (13, 2)):
+        H1, H2 = inputs.chain_terms(n)
+        ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+        psi0 = inputs.random_states(1 << n, seed=510 + n, batch=per)
+        fields = [inputs.cos_field(2.0, 1.0 - k / 3) for k in range(per)]
+        fn = np.stack([nodes("CF43", f, tau, nsteps) for f in fields])
+        psi = dev(psi0)
+        probs.append((ham, psi, fn))
+        refs.append((H1, H2, fields, psi0))
+    st = B.magnus_propagate_ragged(c, probs, B.CF43, tau, opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    for (ham, psi, fn), (H1, H2, fields, psi0) in zip(probs, refs):
+        out = host(psi)
+        for k in range(len(fields)):
+            P = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[k])
+            assert rel(out[k], mg.propagate("CF43", P, tau, nsteps, psi0[k], expm="taylor")) <= BUDGET
+    assert st["exponentials"] == 3 * nsteps * 5
+    c.close()

@@ -409,3 +409,59 @@ def test_dense_batched_mfma_matches_oracle(reserve, per_state):
         ref = mg.propagate("CF4", mg.two_term(H0, V, fields[k]), tau, nsteps, psi0[k], expm="eig")
         assert rel(out[k], ref) <= BUDGET, k
     c.close()
+
+
+@pytest.mark.parametrize("persist", ["1", "0"])
+def test_small_state_propagation_paths_agree(persist, monkeypatch):
+    """Small states run whole propagations in one workgroup each (MAGNUS_PERSIST=1)
+    or as per-iteration launches (0); both match the oracle, with checkpoints."""
+    monkeypatch.setenv("MAGNUS_PERSIST", persist)
+    n, tau, nsteps, k = 10, 0.01, 30, 7
+    H1, H2 = chain(n)
+    c = B.Context(max_dim=1 << n, max_batch=3)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    psi0 = inputs.random_states(1 << n, seed=8, batch=3)
+    fields = [inputs.cos_field(2.0, a) for a in (1.0, -0.5, 2.0)]
+    fn = np.stack([_field_nodes("CF4", f, 0.0, tau, nsteps) for f in fields])
+    nck = (nsteps + k - 1) // k + 1
+    ck = torch.zeros((nck, 3, 1 << n), dtype=torch.complex128, device="cuda")
+    psi = dev(psi0)
+    _, st = B.propagate(c, ham, B.CF4, tau, fn, psi, checkpoints=ck, every_k=k,
+                        opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    out, ck = host(psi), host(ck)
+    for j in range(3):
+        P = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[j])
+        ref, snaps = mg.propagate("CF4", P, tau, nsteps, psi0[j], expm="taylor", every=k)
+        assert rel(out[j], ref) <= BUDGET
+        for q, snap in enumerate(snaps):
+            assert rel(ck[q, j], snap) <= BUDGET
+        assert rel(ck[-1, j], ref) <= BUDGET
+    assert st["exponentials"] == 2 * nsteps * 3
+    assert 0 < st["iters"] <= st["planned_iters"]
+    c.close()
+
+
+def test_ragged_batch_matches_oracle():
+    """Chains of 8, 10, 12 and 15 spins with several states each, one call; the
+    three small problems share one persistent launch, the n = 15 chain runs batched."""
+    tau, nsteps = 0.01, 12
+    c = B.Context(max_dim=1 << 15, max_batch=4)
+    probs, refs = [], []
+    for n, per in ((8, 3), (10, 2), (12, 4), (15, 2)):
+        H1, H2 = chain(n)
+        ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+        psi0 = inputs.random_states(1 << n, seed=300 + n, batch=per)
+        fields = [inputs.cos_field(2.0, 1.0 + k / 16) for k in range(per)]
+        fn = np.stack([_field_nodes("CF4", f, 0.0, tau, nsteps) for f in fields])
+        psi = dev(psi0)
+        probs.append((ham, psi, fn))
+        refs.append((H1, H2, fields, psi0))
+    st = B.magnus_propagate_ragged(c, probs, B.CF4, tau, opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    for (ham, psi, fn), (H1, H2, fields, psi0) in zip(probs, refs):
+        out = host(psi)
+        for k in (0, len(fields) - 1):
+            P = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[k])
+            ref = mg.propagate("CF4", P, tau, nsteps, psi0[k], expm="taylor")
+            assert rel(out[k], ref) <= BUDGET
+    assert st["exponentials"] == 2 * nsteps * (3 + 2 + 4 + 2)
+    c.close()

@@ -138,3 +138,16 @@ def test_null_context_errors_on_host():
     assert L.propagate(None, None, 7, 0.1, 1, None, 1, None, 1, None, 1, None, None, None) == B.EINVAL
     assert b"unknown method" in L.magnus_last_error()
     assert L.magnus_destroy(None) == B.OK
+
+
+@pytest.mark.parametrize("method,q", [("CF4", 2), ("M4", 2), ("M2", 1), ("CF43", 3)])
+def test_method_nodes_are_gauss_legendre(method, q):
+    """The quadrature nodes of every method are the q-point Gauss-Legendre nodes of the step."""
+    assert B.magnus_method_nodes(B.METHODS[method]) == q
+    x, _ = np.polynomial.legendre.leggauss(q)
+    t = B.magnus_quadrature_nodes(B.METHODS[method], 1.5, 0.2, 4)
+    assert t.shape == (4, q)
+    for n in range(4):
+        assert np.allclose(t[n], 1.5 + n * 0.2 + 0.2 * (x + 1) / 2, rtol=0, atol=1e-15)
+    with pytest.raises(B.MagnusError):
+        B.magnus_method_nodes(9)
