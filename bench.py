@@ -167,6 +167,7 @@ def main():
         cpu = cpu_baseline(H1, H2, f, tau, psi0, args.cpu_sample_steps)
         print(f"[bench] cpu oracle: {cpu['value']:.3f} steps/s", file=sys.stderr, flush=True)
 
+    kernel = CSR_KERNEL_NAMES.get(int(os.environ.get("MAGNUS_CSR_VARIANT", "0") or 0), "unknown")
     line = {
         "metric": "Magnus steps/sec (Cf4) and H*v GB/s at 1e-10 error vs FP64 oracle",
         "value": steps_per_s,
@@ -190,13 +191,13 @@ def main():
         "leja_iters_per_step": st["iters"] / K,
         "planned_iters_per_step": st["planned_iters"] / K,
         "roofline": {
-            "kernel": "csr2_iter_kernel<64, kLeja>",
+            "kernel": kernel,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": recorded_traffic(kernel, "chain_n20"),
             "bytes_per_iteration": it_bytes,
             "launches": k_launch,
             "avg_launch_us": avg_ms * 1e3,
@@ -207,6 +208,47 @@ def main():
     line.update(out)
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+CSR_KERNEL_NAMES = {0: "csr2_wave_kernel<8, kLeja>", 1: "csr2_iter_kernel<64, kLeja>", 2: "csr2_rowlane_kernel<64, kLeja>",
+                    3: "csr2_rowlane_kernel<32, kLeja>", 4: "csr2_rowlane_kernel<128, kLeja>",
+                    5: "csr2_wave_kernel<8, kLeja>", 6: "csr2_wave_kernel<16, kLeja>"}
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the sources of the CSR iteration kernels (their file, its header and
+    the device helpers): counters taken from another version of them do not apply."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1709_06483_amd", "csrc")
+    for name in ("kernels.hip", "kernels.h", "device_common.h"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed counter summary (a line
+    'traffic-record: {json}' in profiles/*.md) taken on the current kernel source,
+    else None."""
+    digest = kernel_source_digest()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for ln in fh:
+                if not ln.startswith("traffic-record:"):
+                    continue
+                try:
+                    rec = json.loads(ln.split(":", 1)[1])
+                except ValueError:
+                    continue
+                if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("source_sha256") == digest:
+                    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
 
 
 def _timed(fn):
