@@ -58,6 +58,8 @@ extern "C" {
 #define MAGNUS_M4   1   /* Section 2, Method M4: 2 Gauss nodes, 1 exponential with the commutator */
 #define MAGNUS_M2   2   /* Section 2, exponential midpoint rule (order 2): 1 node, 1 exponential */
 #define MAGNUS_CF43 3   /* Section 2, Method Cf4:3: 3 Gauss nodes, 3 exponentials */
+#define MAGNUS_M6   4   /* Section 2, Method M6: 3 Gauss nodes, 1 exponential with nested commutators
+                           (dense terms, after magnus_dense_m6_prepare) */
 
 /* Largest interpolation degree per substep the library plans for. */
 #define MAGNUS_MAX_DEGREE 64
@@ -167,6 +169,20 @@ int magnus_reserve_dense(magnus_ctx* ctx, int64_t dim);
  * max_dim), EHIP. */
 int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
 
+/* Prepare Method M6 (Section 2) on two dense terms.  For H(t) = H1 + f(t) H2
+ * the nested commutators of the M6 exponent expand into a linear combination,
+ * with scalars that depend on the step's three field samples, of ten fixed
+ * Hermitian matrices: H1, H2, K = i[H1,H2], P_a = -i[H_a,K] (a = 1, 2),
+ * U_11 = i[H1,P_1], U_12 = i[H1,P_2] (= i[H2,P_1]), U_22 = i[H2,P_2],
+ * R_a = -i[K,P_a].  This call forms K as magnus_dense_commutator does and the
+ * seven others with one FP64-MFMA GEMM each, plus their Gershgorin
+ * enclosures, and keeps them in the context (it allocates 7 dim^2 complex128
+ * more); each M6 step then assembles its exponent from the ten (one pass
+ * over them) and runs one Leja exponential, the spectral enclosure summed
+ * over the ten (Weyl).  The matrices belong to this pair of terms, as for
+ * magnus_dense_commutator.  Synchronous.  Errors as magnus_dense_commutator. */
+int magnus_dense_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
+
 /* Free the workspace and the context (NULL is accepted). */
 int magnus_destroy(magnus_ctx* ctx);
 
@@ -222,9 +238,10 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
  * control flow stays on the host, Section 3).  Methods: MAGNUS_CF4, MAGNUS_M4,
  * MAGNUS_M2 (exp(tau A(t_n + tau/2))), MAGNUS_CF43 (Method Cf4:3: three
  * exponentials exp(tau sum_j alpha_ij A_j) on the three Gauss nodes
- * c = 1/2 -+ sqrt(15)/10, 1/2, the factor of the last row acting first).
+ * c = 1/2 -+ sqrt(15)/10, 1/2, the factor of the last row acting first),
+ * MAGNUS_M6 (dense terms prepared by magnus_dense_m6_prepare; states in turn).
  *   f_nodes     HOST double[batch_f][nsteps][q]: f(t_n + c_j tau), j < q, with
- *               q = magnus_method_nodes(method) (2, 2, 1, 3).
+ *               q = magnus_method_nodes(method) (2, 2, 1, 3, 3).
  *   batch_f     1 (one field for all states) or batch (one field per state).
  *   checkpoints NULL, or DEVICE storage for ceil(nsteps/every_k)+1 copies of psi:
  *               slot j receives psi after j*every_k steps (slot 0 = psi0), and
@@ -312,7 +329,7 @@ int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t*
 /* ---- host planning helpers (pure host code, no device needed) ------------------- */
 
 /* Field samples per step of `method` (Section 2): 2 for Cf4 and M4 (two
- * Gauss nodes), 1 for M2 (midpoint), 3 for Cf4:3 (three Gauss nodes);
+ * Gauss nodes), 1 for M2 (midpoint), 3 for Cf4:3 and M6 (three Gauss nodes);
  * EINVAL for an unknown method. */
 int magnus_method_nodes(int32_t method);
 

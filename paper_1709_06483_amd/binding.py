@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libmagnus.so")
 
 OK, EINVAL, EDOMAIN, ENOCONV, EHIP, ENOMEM, ENAN = 0, -1, -2, -3, -4, -5, -6
 CSR, DENSE = 0, 1
-CF4, M4, M2, CF43 = 0, 1, 2, 3
+CF4, M4, M2, CF43, M6 = 0, 1, 2, 3, 4
 MAX_DEGREE = 64
-METHODS = {"CF4": CF4, "M4": M4, "M2": M2, "CF43": CF43}
+METHODS = {"CF4": CF4, "M4": M4, "M2": M2, "CF43": CF43, "M6": M6}
 
 
 class MagnusError(RuntimeError):
@@ -66,7 +66,7 @@ EXPORTS = ("magnus_create", "magnus_destroy", "magnus_last_error", "magnus_check
            "magnus_leja_points", "magnus_divided_differences", "magnus_leja_error", "magnus_leja_plan",
            "magnus_timing", "magnus_timing_read", "magnus_reserve_dense", "magnus_adjoint_workspace_bytes",
            "magnus_propagate_adjoint", "magnus_propagate_ragged", "magnus_method_nodes",
-           "magnus_dense_commutator")
+           "magnus_dense_commutator", "magnus_dense_m6_prepare")
 KERNEL_PERSIST = 6
 KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA, KERNEL_CSR_MULTI, KERNEL_DENSE_MFMA = 0, 1, 2, 3, 4, 5
 
@@ -102,6 +102,7 @@ def lib():
         "magnus_timing_read": (C.c_int, [vp, i32, P(dbl), P(i64)]),
         "magnus_reserve_dense": (C.c_int, [vp, i64]),
         "magnus_dense_commutator": (C.c_int, [vp, P(Hamiltonian), vp]),
+        "magnus_dense_m6_prepare": (C.c_int, [vp, P(Hamiltonian), vp]),
         "magnus_adjoint_workspace_bytes": (i64, [i64, i64, i32]),
         "magnus_propagate_ragged": (C.c_int, [vp, P(Problem), i32, i32, dbl, i64, P(LejaOpts), P(Stats), vp]),
         "magnus_propagate_adjoint": (C.c_int, [vp, P(Hamiltonian), dbl, i64, P(dbl), P(dbl), i32, vp, vp, i32, vp,
@@ -270,6 +271,12 @@ def magnus_spectral_bounds(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamilt
 def magnus_dense_commutator(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:
     """Assemble K = i[H1, H2] of dense terms in the context (needed for M4 on dense terms)."""
     _check(lib().magnus_dense_commutator(ctx.handle, C.byref(ham.struct), _stream()))
+    return ham
+
+
+def magnus_dense_m6_prepare(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:
+    """Assemble the fixed commutator matrices of M6 for dense terms in the context."""
+    _check(lib().magnus_dense_m6_prepare(ctx.handle, C.byref(ham.struct), _stream()))
     return ham
 
 

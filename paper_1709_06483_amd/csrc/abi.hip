@@ -81,6 +81,12 @@ struct magnus_ctx {
   const void* comm_h1 = nullptr;  // the dense pair K belongs to (value pointers, dim, ld)
   const void* comm_h2 = nullptr;
   int64_t comm_n = 0, comm_ld = 0;
+  // magnus_dense_m6_prepare: the nested commutators of M6, kM6Mats matrices of
+  // m6_dim^2 entries, with Gershgorin enclosures, for the pair K belongs to
+  double2* m6 = nullptr;
+  int64_t m6_dim = 0;
+  bool m6_ready = false;
+  double m6_lo[7] = {0, 0, 0, 0, 0, 0, 0}, m6_hi[7] = {0, 0, 0, 0, 0, 0, 0};
   double* partials = nullptr;  // npartials doubles
   size_t npartials = 0;
   int64_t max_grid = 0;
@@ -221,6 +227,8 @@ struct ExpOp {
   const magnus_hamiltonian* h;
   double a, b, kappa;
   const double2* assembled = nullptr;  // dense: the exponent assembled (row stride dim), used with a = 1
+  bool has_interval = false;           // spectral enclosure given (else Weyl from a, b, kappa)
+  double lo = 0.0, hi = 0.0;
 };
 
 // Whether the context holds K = i[H1, H2] of this pair of dense terms.
@@ -336,9 +344,10 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
     acc->exponentials += 1;
     return MAGNUS_OK;
   }
-  double lo, hi;
-  magnus::weyl_interval(op.a, op.h->H1.lam_min, op.h->H1.lam_max, op.b, op.h->H2.lam_min, op.h->H2.lam_max,
-                        op.kappa, op.h->k_min, op.h->k_max, &lo, &hi);
+  double lo = op.lo, hi = op.hi;
+  if (!op.has_interval)
+    magnus::weyl_interval(op.a, op.h->H1.lam_min, op.h->H1.lam_max, op.b, op.h->H2.lam_min, op.h->H2.lam_max,
+                          op.kappa, op.h->k_min, op.h->k_max, &lo, &hi);
   ExpPlan P;
   if (!magnus::plan_exponential(tau, lo, hi, tol_e, o->max_degree, o->max_substeps, &P))
     return fail(MAGNUS_ENOCONV, "no degree <= %d with <= %d substeps reaches tol %g (theta %g)",
@@ -349,7 +358,8 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
   // cheaper than reading both terms in every iteration (16 dim^2 bytes more
   // each), and always for a commutator exponent (K itself is assembled).
   ExpOp it = op;
-  if (op.h->H1.format == MAGNUS_DENSE && (op.kappa != 0.0 || (ctx->assembled_dim >= dim && m * ns >= 4))) {
+  if (!op.assembled && op.h->H1.format == MAGNUS_DENSE &&
+      (op.kappa != 0.0 || (ctx->assembled_dim >= dim && m * ns >= 4))) {
     if (op.kappa != 0.0 && !dense_comm_ready(ctx, op.h))
       return fail(MAGNUS_EINVAL, "dense commutator exponents need magnus_dense_commutator for this pair of terms");
     if (ctx->assembled_dim < dim) return fail(MAGNUS_ENOMEM, "no assembly buffer (magnus_reserve_dense)");
@@ -457,6 +467,66 @@ int m4_state(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, double f1
   const double fbar = 0.5 * (f1 + f2);
   const double kappa = magnus::kSqrt3 * tau * (f2 - f1) / 12.0;
   return run_exponential(ctx, ExpOp{h, 1.0, fbar, kappa}, tau, in, out, tol_e, o, acc, s);
+}
+
+// Whether the context holds the M6 commutators of this pair of dense terms.
+bool dense_m6_ready(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  return ctx->m6_ready && dense_comm_ready(ctx, h);
+}
+
+// One step of Method M6 on one state, dense terms.  With A_j = -i(H1 + f_j H2)
+// the exponent's B_1 = -i tau Hm (Hm = H1 + f_2 H2) and B_2 = -i b2 H2,
+// B_3 = -i b3 H2 with b2 = sqrt(15)/3 tau (f3 - f1), b3 = 10/3 tau (f3 - 2 f2 + f1).
+// Expanding the nested commutators of the M6 exponent in H1, H2 makes it a
+// linear combination, with step-dependent scalars, of ten fixed Hermitian
+// matrices: H1, H2, K = i[H1,H2], P_a = -i[H_a,K], U_ab = i[H_a,P_b]
+// (U_12 = U_21 by the Jacobi identity) and R_a = -i[K,P_a].  The step
+// assembles -i tau (sum_t c_t M_t) once and runs one Leja exponential on it.
+int m6_state(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, const double* f, const double2* in,
+             double2* out, double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  const int64_t dim = h->H1.dim;
+  const double f1 = f[0], f2 = f[1], f3 = f[2];
+  const double r15 = 3.8729833462074168852;
+  const double b2 = r15 / 3.0 * tau * (f3 - f1);
+  const double b3 = 10.0 / 3.0 * tau * (f3 - 2.0 * f2 + f1);
+  // coefficients of H1, H2, K, P1, P2, U11, U12, U22, R1, R2 in the exponent / (-i tau)
+  const double c[10] = {1.0,
+                        f2 + b3 / (12.0 * tau),
+                        b2 / 12.0,
+                        -tau * b3 / 360.0,
+                        (-(2.0 * tau * b3 * f2 / 3.0) - b3 * b3 / 30.0 + b2 * b2) / 240.0,
+                        tau * tau * b2 / 720.0,
+                        (2.0 * tau * tau * b2 * f2 / 3.0 + tau * b2 * b3 / 60.0) / 240.0,
+                        (tau * tau * b2 * f2 * f2 / 3.0 + tau * b2 * b3 * f2 / 60.0) / 240.0,
+                        -tau * tau * b2 * b2 / 14400.0,
+                        -tau * tau * b2 * b2 * f2 / 14400.0};
+  const double mlo[10] = {h->H1.lam_min, h->H2.lam_min, h->k_min, ctx->m6_lo[0], ctx->m6_lo[1], ctx->m6_lo[2],
+                          ctx->m6_lo[3], ctx->m6_lo[4], ctx->m6_lo[5], ctx->m6_lo[6]};
+  const double mhi[10] = {h->H1.lam_max, h->H2.lam_max, h->k_max, ctx->m6_hi[0], ctx->m6_hi[1], ctx->m6_hi[2],
+                          ctx->m6_hi[3], ctx->m6_hi[4], ctx->m6_hi[5], ctx->m6_hi[6]};
+  // Weyl: the spectrum of a sum of Hermitian matrices lies in the sum of their enclosures
+  double lo = 0.0, hi = 0.0;
+  magnus::AssembleTerms T{};
+  T.nterms = 10;
+  for (int t = 0; t < 10; ++t) {
+    lo += std::fmin(c[t] * mlo[t], c[t] * mhi[t]);
+    hi += std::fmax(c[t] * mlo[t], c[t] * mhi[t]);
+    T.c[t] = c[t];
+    if (t < 2) {
+      T.m[t] = reinterpret_cast<const double2*>(t == 0 ? h->H1.val : h->H2.val);
+      T.ld[t] = h->H1.ld;
+    } else {
+      T.m[t] = t == 2 ? ctx->comm : ctx->m6 + (size_t)(t - 3) * (size_t)ctx->m6_dim * (size_t)ctx->m6_dim;
+      T.ld[t] = dim;
+    }
+  }
+  if (ctx->assembled_dim < dim) return fail(MAGNUS_ENOMEM, "no assembly buffer (magnus_reserve_dense)");
+  HIP_TRY(magnus::launch_assemble_terms(T, (int)dim, ctx->assembled, s));
+  ExpOp op{h, 1.0, 0.0, 0.0, ctx->assembled};
+  op.has_interval = true;
+  op.lo = lo;
+  op.hi = hi;
+  return run_exponential(ctx, op, tau, in, out, tol_e, o, acc, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -909,10 +979,11 @@ int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_strea
     ctx->comm_dim = dim;
   }
   ctx->comm_h1 = ctx->comm_h2 = nullptr;
+  ctx->m6_ready = false;
   const double2* H1 = reinterpret_cast<const double2*>(h->H1.val);
   const double2* H2 = reinterpret_cast<const double2*>(h->H2.val);
   HIP_TRY(magnus::launch_zgemm(H1, h->H1.ld, H2, h->H2.ld, ctx->assembled, (int)dim, s));
-  HIP_TRY(magnus::launch_commutator_combine(ctx->assembled, (int)dim, ctx->comm, s));
+  HIP_TRY(magnus::launch_commutator_combine(ctx->assembled, (int)dim, 1.0, ctx->comm, s));
   magnus_term kt{};
   kt.format = MAGNUS_DENSE;
   kt.dim = dim;
@@ -929,6 +1000,58 @@ int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_strea
   return MAGNUS_OK;
 }
 
+int magnus_dense_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream) {
+  int rc = magnus_dense_commutator(ctx, h, stream);
+  if (rc) return rc;
+  const int64_t dim = h->H1.dim;
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->m6_dim < dim) {
+    if (ctx->m6) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(ctx->m6));
+      ctx->m6 = nullptr;
+      ctx->m6_dim = 0;
+    }
+    HIP_TRY(hipMalloc(&ctx->m6, 7 * sizeof(double2) * (size_t)dim * (size_t)dim));
+    ctx->m6_dim = dim;
+  }
+  const size_t sz = (size_t)ctx->m6_dim * (size_t)ctx->m6_dim;
+  double2* M = ctx->m6;
+  double2* P1 = M;
+  double2* P2 = M + sz;
+  const double2* H1 = reinterpret_cast<const double2*>(h->H1.val);
+  const double2* H2 = reinterpret_cast<const double2*>(h->H2.val);
+  const long long ld = h->H1.ld;
+  // (left, ld, right, ld, scale, out): out = scale i [left, right], the GEMM product in the assembly buffer
+  struct Job {
+    const double2* a;
+    long long lda;
+    const double2* b;
+    long long ldb;
+    double scale;
+    double2* out;
+  };
+  const Job jobs[7] = {{H1, ld, ctx->comm, dim, -1.0, P1},           // P1 = -i[H1, K]
+                       {H2, ld, ctx->comm, dim, -1.0, P2},           // P2 = -i[H2, K]
+                       {H1, ld, P1, dim, 1.0, M + 2 * sz},           // U11 = i[H1, P1]
+                       {H1, ld, P2, dim, 1.0, M + 3 * sz},           // U12 = i[H1, P2]
+                       {H2, ld, P2, dim, 1.0, M + 4 * sz},           // U22 = i[H2, P2]
+                       {ctx->comm, dim, P1, dim, -1.0, M + 5 * sz},  // R1 = -i[K, P1]
+                       {ctx->comm, dim, P2, dim, -1.0, M + 6 * sz}}; // R2 = -i[K, P2]
+  for (int j = 0; j < 7; ++j) {
+    HIP_TRY(magnus::launch_zgemm(jobs[j].a, jobs[j].lda, jobs[j].b, jobs[j].ldb, ctx->assembled, (int)dim, s));
+    HIP_TRY(magnus::launch_commutator_combine(ctx->assembled, (int)dim, jobs[j].scale, jobs[j].out, s));
+    magnus_term t{};
+    t.format = MAGNUS_DENSE;
+    t.dim = dim;
+    t.ld = dim;
+    t.val = jobs[j].out;
+    if ((rc = dense_scan(ctx, t, s, &ctx->m6_lo[j], &ctx->m6_hi[j]))) return rc;
+  }
+  ctx->m6_ready = true;
+  return MAGNUS_OK;
+}
+
 int magnus_destroy(magnus_ctx* ctx) {
   if (!ctx) return MAGNUS_OK;
   (void)hipSetDevice(ctx->device);
@@ -938,6 +1061,7 @@ int magnus_destroy(magnus_ctx* ctx) {
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->assembled) (void)hipFree(ctx->assembled);
   if (ctx->comm) (void)hipFree(ctx->comm);
+  if (ctx->m6) (void)hipFree(ctx->m6);
   if (ctx->partials) (void)hipFree(ctx->partials);
   if (ctx->scan) (void)hipFree(ctx->scan);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -1076,7 +1200,7 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
               int32_t every_k, const magnus_leja_opts* opts, magnus_stats* stats, magnus_stream stream) {
   magnus::Scheme S;
   if (!magnus::method_scheme(method, &S)) return fail(MAGNUS_EINVAL, "unknown method %d", method);
-  int rc = check_ham(ctx, h, method == MAGNUS_M4);
+  int rc = check_ham(ctx, h, S.commutator);
   if (rc) return rc;
   if ((rc = check_opts(opts)) || (rc = check_batch(ctx, batch))) return rc;
   if (!psi) return fail(MAGNUS_EINVAL, "null state pointer");
@@ -1089,6 +1213,8 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
     if (!is_fin(f_nodes[k])) return fail(MAGNUS_EDOMAIN, "non-finite field value at node %lld", (long long)k);
   if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR && !dense_comm_ready(ctx, h))
     return fail(MAGNUS_EINVAL, "M4 on dense terms needs magnus_dense_commutator for this pair of terms");
+  if (S.sixth && (h->H1.format != MAGNUS_DENSE || !dense_m6_ready(ctx, h)))
+    return fail(MAGNUS_EINVAL, "M6 needs dense terms prepared by magnus_dense_m6_prepare");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = begin_call(ctx, s))) return rc;
   if ((rc = ensure_valid(ctx, h, s))) return rc;
@@ -1137,8 +1263,9 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
           double2* y = st + c * dim;
           double fv[3];
           for (int j = 0; j < S.q; ++j) fv[j] = fval(c, k, j);
-          rc = S.commutator ? m4_state(ctx, h, tau, fv[0], fv[1], y, y, tol_e, opts, &acc, s)
-                            : cf_state(ctx, h, S, tau, fv, y, y, tol_e, opts, &acc, s);
+          rc = S.sixth        ? m6_state(ctx, h, tau, fv, y, y, tol_e, opts, &acc, s)
+               : S.commutator ? m4_state(ctx, h, tau, fv[0], fv[1], y, y, tol_e, opts, &acc, s)
+                              : cf_state(ctx, h, S, tau, fv, y, y, tol_e, opts, &acc, s);
           if (rc) return rc;
         }
       }

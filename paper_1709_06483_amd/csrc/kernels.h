@@ -151,8 +151,18 @@ hipError_t launch_dense_assemble(const double2* H1, const double2* H2, long long
 // C = A B (n x n complex128, row strides lda, ldb in, n out) on the FP64 matrix cores.
 hipError_t launch_zgemm(const double2* A, long long lda, const double2* B, long long ldb, double2* C, int n,
                         hipStream_t s);
-// K = i (C - C^H), n x n with row stride n.
-hipError_t launch_commutator_combine(const double2* C, int n, double2* K, hipStream_t s);
+// K = scale i (C - C^H), n x n with row stride n.
+hipError_t launch_commutator_combine(const double2* C, int n, double scale, double2* K, hipStream_t s);
+
+// out = sum_t c[t] m[t] (m[t] with row stride ld[t], out with row stride n).
+constexpr int kMaxAssembleTerms = 10;
+struct AssembleTerms {
+  const double2* m[kMaxAssembleTerms];
+  long long ld[kMaxAssembleTerms];
+  double c[kMaxAssembleTerms];
+  int nterms;
+};
+hipError_t launch_assemble_terms(const AssembleTerms& T, int n, double2* out, hipStream_t s);
 
 // Dense Frechet block iteration (B == 2 interleaved pair, joint stop test);
 // decide with dense_frechet_grid(dim) workgroups.

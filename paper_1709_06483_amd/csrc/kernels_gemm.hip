@@ -1,7 +1,7 @@
-// The commutator K = i [H1, H2] of two dense Hermitian terms, assembled once
-// per pair for Method M4 (Section 2) on dense terms.  Since H1 H2 and H2 H1
-// are adjoint to each other, one complex GEMM C = H1 H2 suffices:
-// K = i (C - C^H).
+// Commutators of dense Hermitian matrices, assembled once per pair of terms
+// for Methods M4 and M6 (Section 2) on dense terms.  For Hermitian A, B the
+// products A B and B A are adjoint to each other, so one complex GEMM
+// C = A B gives the Hermitian i [A, B] = i (C - C^H).
 //
 // The GEMM runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64, four real
 // products per complex 16x16x4 step).  A workgroup of four waves computes a
@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kThreads) void zgemm_kernel(const double2* A, long 
       }
 }
 
-// K[r][c] = i (C[r][c] - conj(C[c][r])), C and K n x n with row stride n.
-__global__ __launch_bounds__(256) void commutator_combine_kernel(const double2* C, int n, double2* K) {
+// K[r][c] = s i (C[r][c] - conj(C[c][r])), C and K n x n with row stride n.
+__global__ __launch_bounds__(256) void commutator_combine_kernel(const double2* C, int n, double sc, double2* K) {
   __shared__ double2 t[32][33];
   const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;  // 32 x 8 threads
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
@@ -111,12 +111,31 @@ __global__ __launch_bounds__(256) void commutator_combine_kernel(const double2* 
     if (r < n && c < n) {
       const double2 a = C[(long long)r * n + c];
       const double2 b = t[tx][ty];  // C[c][r]
-      K[(long long)r * n + c] = make_double2(-(a.y + b.y), a.x - b.x);
+      K[(long long)r * n + c] = make_double2(-sc * (a.y + b.y), sc * (a.x - b.x));
     }
   }
 }
 
+// out = sum_t c_t M_t (out row stride n).
+__global__ __launch_bounds__(kThreads) void assemble_terms_kernel(AssembleTerms T, int n, double2* __restrict__ out) {
+  const long long total = (long long)n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / n, c = i % n;
+    d2 h = {0.0, 0.0};
+    for (int t = 0; t < T.nterms; ++t)
+      h += rmul(T.c[t], __builtin_nontemporal_load(reinterpret_cast<const d2*>(T.m[t]) + r * T.ld[t] + c));
+    out[i] = fromd2(h);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_assemble_terms(const AssembleTerms& T, int n, double2* out, hipStream_t s) {
+  if (T.nterms < 1 || T.nterms > kMaxAssembleTerms) return hipErrorInvalidValue;
+  assemble_terms_kernel<<<4096, kThreads, 0, s>>>(T, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_zgemm(const double2* A, long long lda, const double2* B, long long ldb, double2* C, int n,
                         hipStream_t s) {
@@ -125,9 +144,9 @@ hipError_t launch_zgemm(const double2* A, long long lda, const double2* B, long 
   return hipGetLastError();
 }
 
-hipError_t launch_commutator_combine(const double2* C, int n, double2* K, hipStream_t s) {
+hipError_t launch_commutator_combine(const double2* C, int n, double scale, double2* K, hipStream_t s) {
   const unsigned g = (unsigned)((n + 31) / 32);
-  commutator_combine_kernel<<<dim3(g, g), 256, 0, s>>>(C, n, K);
+  commutator_combine_kernel<<<dim3(g, g), 256, 0, s>>>(C, n, scale, K);
   return hipGetLastError();
 }
 

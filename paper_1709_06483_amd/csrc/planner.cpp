@@ -400,6 +400,17 @@ bool method_scheme(int method, Scheme* out) {
       }
       break;
     }
+    case 4: {  // M6 on the three Gauss nodes (one exponential; coefficients built by the caller)
+      const double r15 = 3.8729833462074168852;
+      S.q = 3;
+      S.nexp = 1;
+      S.commutator = true;
+      S.sixth = true;
+      S.c[0] = 0.5 - r15 / 10.0;
+      S.c[1] = 0.5;
+      S.c[2] = 0.5 + r15 / 10.0;
+      break;
+    }
     default:
       return false;
   }

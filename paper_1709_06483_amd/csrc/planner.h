@@ -103,13 +103,14 @@ constexpr double kAlpha2 = (3.0 + 2.0 * kSqrt3) / 12.0;
 struct Scheme {
   int q = 0;
   int nexp = 0;
-  bool commutator = false;
+  bool commutator = false;  // M4, M6: one exponential with commutator terms
+  bool sixth = false;       // M6 (its exponent is assembled from precomputed commutators)
   double c[3] = {0, 0, 0};
   double rho[3] = {0, 0, 0};
   double w[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 };
 
-// Method ids as in the public header: 0 Cf4, 1 M4, 2 M2, 3 Cf4:3.
+// Method ids as in the public header: 0 Cf4, 1 M4, 2 M2, 3 Cf4:3, 4 M6.
 bool method_scheme(int method, Scheme* out);
 
 }  // namespace magnus

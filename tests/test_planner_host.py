@@ -140,7 +140,7 @@ def test_null_context_errors_on_host():
     assert L.magnus_destroy(None) == B.OK
 
 
-@pytest.mark.parametrize("method,q", [("CF4", 2), ("M4", 2), ("M2", 1), ("CF43", 3)])
+@pytest.mark.parametrize("method,q", [("CF4", 2), ("M4", 2), ("M2", 1), ("CF43", 3), ("M6", 3)])
 def test_method_nodes_are_gauss_legendre(method, q):
     """The quadrature nodes of every method are the q-point Gauss-Legendre nodes of the step."""
     assert B.magnus_method_nodes(B.METHODS[method]) == q
