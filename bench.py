@@ -215,15 +215,28 @@ CSR_KERNEL_NAMES = {0: "csr2_wave_kernel<8, kLeja>", 1: "csr2_iter_kernel<64, kL
                     5: "csr2_wave_kernel<8, kLeja>", 6: "csr2_wave_kernel<16, kLeja>"}
 
 
-def kernel_source_digest() -> str:
-    """sha256 over the sources of the CSR iteration kernels (their file, its header and
-    the device helpers): counters taken from another version of them do not apply."""
+def kernel_source_digest(sources=None) -> str:
+    """sha256 over the source text the CSR iteration kernel is compiled from: its own
+    definition in kernels.hip, the structs it takes (kernels.h) and the device helpers
+    (device_common.h).  Counters taken from another version of these do not apply."""
     import hashlib
-    h = hashlib.sha256()
+    import re
     csrc = os.path.join(ROOT, "paper_1709_06483_amd", "csrc")
-    for name in ("kernels.hip", "kernels.h", "device_common.h"):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(fh.read())
+    if sources is None:
+        sources = {}
+        for name in ("kernels.hip", "kernels.h", "device_common.h"):
+            with open(os.path.join(csrc, name)) as fh:
+                sources[name] = fh.read()
+    k = sources["kernels.hip"]
+    i = k.index("void csr2_wave_kernel(")
+    i = k.rindex("template <int RPW, int MODE>", 0, i)
+    j = k.index("\n// ----", i)
+    h = hashlib.sha256()
+    h.update(k[i:j].encode())
+    for struct in ("Slot", "CsrDev", "IterArgs"):
+        m = re.search(r"struct %s \{.*?\n\};" % struct, sources["kernels.h"], re.S)
+        h.update(m.group(0).encode())
+    h.update(sources["device_common.h"].encode())
     return h.hexdigest()
 
 
@@ -308,6 +321,34 @@ def other_workload(name: str, args):
                      "kernel_avg_us": 1e3 * kms / max(kn, 1),
                      "kernel_gbps": it_bytes * st["iters"] / max(kms * 1e-3, 1e-12) / 1e9,
                      "hv_gbps": it_bytes * st["iters"] / (ms * 1e-3) / 1e9, "tol_per_exp": tol_e})
+        if name == "dense_8192":
+            # the same run with the exponent assembled once per exponential (48 N^2 bytes)
+            # and one matrix read per iteration (16 N^2 + 64 N bytes)
+            ctx.reserve_dense(dim)
+            psi = torch.from_numpy(psi0).cuda()
+            B.propagate(ctx, ham, B.CF4, tau, fn[:W], psi, opts=B.leja_opts(tol_e))
+            ctx.timing(True)
+            ms2, (_, st2) = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, fn[W:], psi,
+                                                        opts=B.leja_opts(tol_e), stats=True))
+            k2, n2 = ctx.timing_read(B.KERNEL_DENSE_LEJA)
+            ctx.timing(False)
+            one = 16 * dim * dim + 64 * dim
+            line["assembled"] = {"steps_per_s": K / (ms2 * 1e-3), "ms_per_step": ms2 / K,
+                                 "leja_iters_per_step": st2["iters"] / K, "kernel_avg_us": 1e3 * k2 / max(n2, 1),
+                                 "kernel_gbps": one * st2["iters"] / max(k2 * 1e-3, 1e-12) / 1e9,
+                                 "hv_gbps": (one * st2["iters"] + 48 * dim * dim * st2["exponentials"])
+                                 / (ms2 * 1e-3) / 1e9}
+            # Method M4 on the dense terms: K = i[H1, H2] by one FP64-MFMA GEMM, then one
+            # assembled exponent H1 + fbar H2 + kappa K per step
+            gms, _ = _timed(lambda: B.magnus_dense_commutator(ctx, ham))
+            fn4 = np.vectorize(f)(B.magnus_quadrature_nodes(B.M4, 0.0, tau, W + K))
+            psi = torch.from_numpy(psi0).cuda()
+            B.propagate(ctx, ham, B.M4, tau, fn4[:W], psi, opts=B.leja_opts(2 * tol_e))
+            ms4, (_, st4) = _timed(lambda: B.propagate(ctx, ham, B.M4, tau, fn4[W:], psi,
+                                                        opts=B.leja_opts(2 * tol_e), stats=True))
+            line["m4"] = {"steps_per_s": K / (ms4 * 1e-3), "ms_per_step": ms4 / K,
+                          "leja_iters_per_step": st4["iters"] / K, "commutator_ms": gms,
+                          "commutator_gemm_tflops": 8.0 * dim ** 3 / (gms * 1e-3) / 1e12}
     elif name == "batched_dense_4096":
         N, Bn, tau = 4096, 256, 0.005
         H0 = inputs.powerlaw_hermitian(N, 1.5, 31)

@@ -302,7 +302,7 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
       return magnus::launch_dense2_iter(reinterpret_cast<const double2*>(h->H1.val),
                                         reinterpret_cast<const double2*>(h->H2.val), dim, h->H1.ld, a, s);
     }));
-    HIP_TRY(magnus::launch_leja_decide(a, magnus::dense2_grid(dim), s));
+    HIP_TRY(magnus::launch_leja_decide(a, magnus::dense2_grid(dim, op.assembled ? 1 : 2), s));
     return MAGNUS_OK;
   }
   CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};

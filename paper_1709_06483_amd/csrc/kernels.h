@@ -86,7 +86,7 @@ int dense_gershgorin_grid(int dim);
 // exponent) when H2 is null.
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s);
-int dense2_grid(int dim);
+int dense2_grid(int dim, int nterms);
 
 // Reduce the norm partials of the iteration launched just before (grid
 // workgroups) and write the early-termination verdict into the slot.

@@ -759,16 +759,17 @@ hipError_t launch_dense_gershgorin(const double2* H, int dim, long long ld, doub
   return hipGetLastError();
 }
 
-constexpr int kDenseRPW = 2;
-int dense2_grid(int dim) {
-  const int rows_per_block = kDenseRPW * (kThreads / 64);
+// Rows per wave: 2 for two terms, 4 for one (the same matrix bytes in flight per lane).
+constexpr int kDenseRPW2 = 2, kDenseRPW1 = 4;
+int dense2_grid(int dim, int nterms) {
+  const int rows_per_block = (nterms == 2 ? kDenseRPW2 : kDenseRPW1) * (kThreads / 64);
   return (dim + rows_per_block - 1) / rows_per_block;
 }
 
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s) {
-  if (H2) dense2_iter_kernel<kDenseRPW, 2><<<dense2_grid(dim), kThreads, 0, s>>>(H1, H2, dim, ld, a);
-  else dense2_iter_kernel<kDenseRPW, 1><<<dense2_grid(dim), kThreads, 0, s>>>(H1, H1, dim, ld, a);
+  if (H2) dense2_iter_kernel<kDenseRPW2, 2><<<dense2_grid(dim, 2), kThreads, 0, s>>>(H1, H2, dim, ld, a);
+  else dense2_iter_kernel<kDenseRPW1, 1><<<dense2_grid(dim, 1), kThreads, 0, s>>>(H1, H1, dim, ld, a);
   return hipGetLastError();
 }
 
