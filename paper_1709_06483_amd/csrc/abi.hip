@@ -624,6 +624,8 @@ int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E
   const int grid = dense ? (E.frechet ? magnus::dense_frechet_grid(dim) : magnus::dense_mfma_row_blocks(dim))
                          : magnus::csr2_multi_grid(dim, B);
   const int mode = E.frechet ? magnus::kMultiFrechet : magnus::kMultiLeja;
+  if (grid <= 0 || (size_t)grid * (size_t)B * 2 > ctx->npartials)
+    return fail(MAGNUS_ENOMEM, "per-workgroup partial sums (%d x %d) exceed the context's buffer", grid, B);
   const double2* D1 = reinterpret_cast<const double2*>(h->H1.val);
   const double2* D2 = reinterpret_cast<const double2*>(h->H2.val);
   long long ldd = h->H1.ld;
@@ -928,7 +930,9 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   if (e == hipSuccess) e = hipMalloc(&c->slots, sizeof(Slot) * c->nslots);
   if (e == hipSuccess) e = hipMalloc(&c->table, sizeof(ColParam) * kTableCap);
   if (e == hipSuccess) e = hipMalloc(&c->arena, kArenaBytes);
-  c->npartials = 2 * (size_t)c->max_grid + (size_t)max_dim * (size_t)std::max(1, max_batch) / 8 + (size_t)max_dim + 64;
+  // the multi-state CSR kernel writes dim * B^2 / 128 doubles (B <= 32: at most 8 dim)
+  c->npartials = 2 * (size_t)c->max_grid + 8 * (size_t)max_dim +
+                 (size_t)max_dim * (size_t)std::max(1, max_batch) / 8 + (size_t)max_dim + 64;
   if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->npartials);
   if (e == hipSuccess) e = hipMalloc(&c->scan, sizeof(double) * (size_t)c->scan_len);
   if (e == hipSuccess) e = hipMemset(c->slots, 0, sizeof(Slot) * c->nslots);

@@ -759,8 +759,9 @@ hipError_t launch_dense_gershgorin(const double2* H, int dim, long long ld, doub
   return hipGetLastError();
 }
 
-// Rows per wave: 2 for two terms, 4 for one (the same matrix bytes in flight per lane).
-constexpr int kDenseRPW2 = 2, kDenseRPW1 = 4;
+// Rows per wave: 2 (with 8192 rows that is 16 waves per CU; more rows per
+// wave leave too few waves to cover the memory latency).
+constexpr int kDenseRPW2 = 2, kDenseRPW1 = 2;
 int dense2_grid(int dim, int nterms) {
   const int rows_per_block = (nterms == 2 ? kDenseRPW2 : kDenseRPW1) * (kThreads / 64);
   return (dim + rows_per_block - 1) / rows_per_block;

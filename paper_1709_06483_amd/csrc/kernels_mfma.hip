@@ -175,7 +175,8 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
   }
   __syncthreads();
   if (tid < TN && col0 + tid < B) {
-    const long long o = ((long long)rb * B + col0 + tid) * 2;
+    // column-major (state, row block), as the decide kernel reads them
+    const long long o = ((long long)(col0 + tid) * (gridDim.x / gx) + rb) * 2;
     a.partials[o] = csum[0][0][tid] + csum[1][0][tid];
     a.partials[o + 1] = csum[0][1][tid] + csum[1][1][tid];
   }

@@ -19,9 +19,10 @@ template <int B, int MODE>
 __global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev t2, int dim, MultiArgs a) {
   constexpr int NWAVE = kThreads / 64;
   constexpr int RP = 64 / B;                // rows per pass: lane = rr * B + b
-  constexpr int RPW = RP >= 16 ? RP : 16;   // rows per wave
+  constexpr int RPW = RP;                   // rows per wave: one pass (with many states the
+                                            // gathers, not the matrix stream, dominate)
   constexpr int NPASS = RPW / RP;
-  constexpr int CAPW = 512;                 // entries staged per chunk
+  constexpr int CAPW = 256;                 // entries staged per chunk
   constexpr int U = CAPW / 64;
   static_assert(MODE != kMultiFrechet || B == 2, "the Frechet block vector has two columns");
   __shared__ d2 sval[NWAVE][CAPW];
@@ -98,8 +99,11 @@ __global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev 
         if (r < nrows) {
           const int s1 = srp[wv][0][r] - base1, e1 = srp[wv][0][r + 1] - base1;
           const int s2 = n1 + srp[wv][1][r] - base2, e2 = n1 + srp[wv][1][r + 1] - base2;
+          // unrolled so several gathers are in flight per lane
+#pragma unroll 8
           for (int k = max(s1, c0); k < min(e1, hi); ++k)
             acc1[q] += cmul(sval[wv][k - c0], x[(long long)scol[wv][k - c0] * B + b]);
+#pragma unroll 8
           for (int k = max(s2, c0); k < min(e2, hi); ++k)
             acc2[q] += cmul(sval[wv][k - c0], x[(long long)scol[wv][k - c0] * B + b]);
         }
@@ -151,8 +155,9 @@ __global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev 
   if (tid < B) {
     double bw = 0.0, bv = 0.0;
     for (int w = 0; w < NWAVE; ++w) { bw += wsum[w][tid][0]; bv += wsum[w][tid][1]; }
-    a.partials[((long long)blockIdx.x * B + tid) * 2] = bw;
-    a.partials[((long long)blockIdx.x * B + tid) * 2 + 1] = bv;
+    // column-major (column tid, workgroup blockIdx.x), so each column's decide reads contiguously
+    a.partials[((long long)tid * gridDim.x + blockIdx.x) * 2] = bw;
+    a.partials[((long long)tid * gridDim.x + blockIdx.x) * 2 + 1] = bv;
   }
 }
 
@@ -166,12 +171,22 @@ __global__ __launch_bounds__(kDecideThreads) void multi_decide_kernel(MultiArgs 
   if (a.check_stop && load_stopped(S)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c_lo = a.joint ? 0 : col, c_hi = a.joint ? a.B : col + 1;
+  // partials are column-major: column c's per-workgroup pairs are contiguous
+  constexpr int kPer = 8;
   double sw = 0.0, sv = 0.0;
-  for (int k = tid; k < grid; k += kDecideThreads)
-    for (int c = c_lo; c < c_hi; ++c) {
-      sw += a.partials[((long long)k * a.B + c) * 2];
-      sv += a.partials[((long long)k * a.B + c) * 2 + 1];
+  for (int c = c_lo; c < c_hi; ++c) {
+    const d2* P = reinterpret_cast<const d2*>(a.partials) + (long long)c * grid;
+    for (int k0 = 0; k0 < grid; k0 += kDecideThreads * kPer) {
+      d2 v[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int k = k0 + u * kDecideThreads + tid;
+        v[u] = k < grid ? P[k] : d2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) { sw += v[u].x; sv += v[u].y; }
     }
+  }
   sw = wave_sum(sw);
   sv = wave_sum(sv);
   if (lane == 0) { red[0][wv] = sw; red[1][wv] = sv; }
@@ -283,8 +298,8 @@ __global__ __launch_bounds__(kThreads) void dense_frechet_kernel(const double2* 
   if (tid < 2) {
     double bw = 0.0, bv = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) { bw += wsum[w][tid][0]; bv += wsum[w][tid][1]; }
-    a.partials[((long long)blockIdx.x * 2 + tid) * 2] = bw;
-    a.partials[((long long)blockIdx.x * 2 + tid) * 2 + 1] = bv;
+    a.partials[((long long)tid * gridDim.x + blockIdx.x) * 2] = bw;
+    a.partials[((long long)tid * gridDim.x + blockIdx.x) * 2 + 1] = bv;
   }
 }
 
@@ -340,10 +355,10 @@ __global__ void frechet_init_kernel(const double2* __restrict__ v, double2* __re
   }
 }
 
+// Must match csr2_multi_kernel's rows per wave (64 / B) times its waves.
 template <int B>
 int multi_rows_per_block() {
-  constexpr int RP = 64 / B;
-  return (RP >= 16 ? RP : 16) * (kThreads / 64);
+  return (64 / B) * (kThreads / 64);
 }
 
 }  // namespace
