@@ -58,6 +58,7 @@ def main():
                     choices=["chain_n20", "chain_n10", "dense_8192", "batched_dense_4096", "ragged_chains",
                              "adjoint_chain_n16"],
                     help="chain_n20 is the headline line; the others print one informational line each")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the size heuristic for the CSR kernel")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -106,6 +107,10 @@ def main():
 
     ctx = B.Context(max_dim=dim)
     ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    tune = B.magnus_autotune(ctx, ham) if not args.no_autotune else None
+    if tune:
+        print(f"[bench] autotune: {tune['variant_name']} "
+              f"({', '.join(f'{k}: {v:.1f} us' for k, v in tune['variant_us'].items())})", file=sys.stderr, flush=True)
     W, K = args.warmup, args.steps
 
     def run(method: str, tol_e: float):
@@ -167,7 +172,8 @@ def main():
         cpu = cpu_baseline(H1, H2, f, tau, psi0, args.cpu_sample_steps)
         print(f"[bench] cpu oracle: {cpu['value']:.3f} steps/s", file=sys.stderr, flush=True)
 
-    kernel = CSR_KERNEL_NAMES.get(int(os.environ.get("MAGNUS_CSR_VARIANT", "0") or 0), "unknown")
+    code = int(os.environ.get("MAGNUS_CSR_VARIANT", "0") or 0) or (tune["variant"] if tune else 0)
+    kernel = CSR_KERNEL_NAMES.get(code, "unknown")
     line = {
         "metric": "Magnus steps/sec (Cf4) and H*v GB/s at 1e-10 error vs FP64 oracle",
         "value": steps_per_s,
@@ -204,6 +210,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
+        "autotune": tune,
     }
     line.update(out)
     print(json.dumps(line), flush=True)
@@ -380,15 +387,18 @@ def other_workload(name: str, args):
         for n in sizes:
             H1, H2 = inputs.chain_terms(n)
             ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+            if not args.no_autotune and (1 << n) > 4096:
+                B.magnus_autotune(ctx, ham, batch=per)
             psi = torch.from_numpy(inputs.random_states(1 << n, seed=300 + n, batch=per)).cuda()
             t = B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K)
             fn = np.stack([np.vectorize(inputs.cos_field(2.0, 1.0 + k / per))(t) for k in range(per)])
             probs.append((ham, psi, fn))
         tol_e = 1e-10 / (2 * 100)
-        for ham, psi, fn in probs:
-            B.propagate(ctx, ham, B.CF4, tau, fn[:, :W], psi, opts=B.leja_opts(tol_e))
-        ms, _ = _timed(lambda: [B.propagate(ctx, ham, B.CF4, tau, fn[:, W:], psi, opts=B.leja_opts(tol_e))
-                                for ham, psi, fn in probs])
+        warm = [(ham, psi, fn[:, :W]) for ham, psi, fn in probs]
+        timed = [(ham, psi, fn[:, W:]) for ham, psi, fn in probs]
+        if W:
+            B.magnus_propagate_ragged(ctx, warm, B.CF4, tau, opts=B.leja_opts(tol_e))
+        ms, _ = _timed(lambda: B.magnus_propagate_ragged(ctx, timed, B.CF4, tau, opts=B.leja_opts(tol_e)))
         line.update({"metric": "ragged batch Cf4 Magnus steps/sec (4 sizes x 16 instances)",
                      "value": K / (ms * 1e-3), "unit": "steps/s", "steps": K, "ms_per_step": ms / K,
                      "instance_steps_per_s": len(sizes) * per * K / (ms * 1e-3)})

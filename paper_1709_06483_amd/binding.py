@@ -66,7 +66,7 @@ EXPORTS = ("magnus_create", "magnus_destroy", "magnus_last_error", "magnus_check
            "magnus_leja_points", "magnus_divided_differences", "magnus_leja_error", "magnus_leja_plan",
            "magnus_timing", "magnus_timing_read", "magnus_reserve_dense", "magnus_adjoint_workspace_bytes",
            "magnus_propagate_adjoint", "magnus_propagate_ragged", "magnus_method_nodes",
-           "magnus_dense_commutator", "magnus_dense_m6_prepare")
+           "magnus_dense_commutator", "magnus_dense_m6_prepare", "magnus_autotune")
 KERNEL_PERSIST = 6
 KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA, KERNEL_CSR_MULTI, KERNEL_DENSE_MFMA = 0, 1, 2, 3, 4, 5
 
@@ -103,6 +103,7 @@ def lib():
         "magnus_reserve_dense": (C.c_int, [vp, i64]),
         "magnus_dense_commutator": (C.c_int, [vp, P(Hamiltonian), vp]),
         "magnus_dense_m6_prepare": (C.c_int, [vp, P(Hamiltonian), vp]),
+        "magnus_autotune": (C.c_int, [vp, P(Hamiltonian), i32, P(i32), P(i32), P(dbl), P(dbl), vp]),
         "magnus_adjoint_workspace_bytes": (i64, [i64, i64, i32]),
         "magnus_propagate_ragged": (C.c_int, [vp, P(Problem), i32, i32, dbl, i64, P(LejaOpts), P(Stats), vp]),
         "magnus_propagate_adjoint": (C.c_int, [vp, P(Hamiltonian), dbl, i64, P(dbl), P(dbl), i32, vp, vp, i32, vp,
@@ -272,6 +273,23 @@ def magnus_dense_commutator(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamil
     """Assemble K = i[H1, H2] of dense terms in the context (needed for M4 on dense terms)."""
     _check(lib().magnus_dense_commutator(ctx.handle, C.byref(ham.struct), _stream()))
     return ham
+
+
+CSR_VARIANTS = {1: "nonzero streaming", 2: "row per lane, 64 rows", 3: "row per lane, 32 rows",
+                4: "row per lane, 128 rows", 5: "wave tiles of 8 rows", 6: "wave tiles of 16 rows"}
+
+
+def magnus_autotune(ctx: Context, ham: DeviceHamiltonian, batch: int = 1) -> dict:
+    """Time the CSR kernel variants (and multi-state group sizes when batch > 1) on these
+    terms and keep the fastest in the context.  Returns the choices and the timings."""
+    v, g = C.c_int32(), C.c_int32()
+    vus = np.zeros(6)
+    gus = np.zeros(5)
+    _check(lib().magnus_autotune(ctx.handle, C.byref(ham.struct), batch, C.byref(v), C.byref(g), _dptr(vus),
+                                 _dptr(gus), _stream()))
+    return {"variant": int(v.value), "variant_name": CSR_VARIANTS[int(v.value)], "group": int(g.value),
+            "variant_us": {CSR_VARIANTS[k + 1]: float(vus[k]) for k in range(6)},
+            "group_us": {str(b): (None if np.isnan(gus[i]) else float(gus[i])) for i, b in enumerate((2, 4, 8, 16, 32))}}
 
 
 def magnus_dense_m6_prepare(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <set>
 #include <string>
@@ -61,6 +62,8 @@ constexpr size_t kTableCap = 1 << 18;
 constexpr size_t kArenaBytes = 8u << 20;
 // States of at most this many entries run whole propagations in one workgroup.
 constexpr int64_t kSmallDim = magnus::kPersistMaxDim;
+// Row mappings magnus_autotune times (variant codes 1..kTuneVariants).
+constexpr int kTuneVariants = 6;
 
 }  // namespace
 
@@ -97,6 +100,9 @@ struct magnus_ctx {
   // kernel timing: (kind, start, stop) per recorded launch, events reused from a pool
   int csr_variant = 0;  // MAGNUS_CSR_VARIANT: 0 auto (wave tiles of 8 rows from 65536 rows on),
                         // 1 nonzero-streaming, 2-4 row-per-lane (64/32/128 rows), 5-6 wave tiles (8/16 rows)
+  // magnus_autotune results, per CSR term pair (H1 row_ptr, dim): the variant code
+  // of the single-state iteration and the states per multi-state pass
+  std::map<std::pair<const void*, int64_t>, int> tuned_variant, tuned_group;
   bool timing = false;
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;
   std::vector<hipEvent_t> pool;
@@ -237,14 +243,24 @@ bool dense_comm_ready(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
          ctx->comm_ld == h->H1.ld;
 }
 
-int rows_per_block(magnus_ctx* ctx, int64_t dim) {
-  if (ctx->csr_variant == 1) return dim >= 65536 ? 64 : 16;
-  if (ctx->csr_variant == 2) return magnus::kRowLane;
-  if (ctx->csr_variant == 3) return -32;
-  if (ctx->csr_variant == 4) return -128;
-  if (ctx->csr_variant == 5) return magnus::kWaveTile + 8;
-  if (ctx->csr_variant == 6) return magnus::kWaveTile + 16;
-  return dim >= 65536 ? magnus::kWaveTile + 8 : 16;
+// Row mapping of the single-state CSR iteration for a variant code (the
+// MAGNUS_CSR_VARIANT numbering; 0 = the size heuristic).
+int variant_rows(int code, int64_t dim) {
+  switch (code) {
+    case 1: return dim >= 65536 ? 64 : 16;
+    case 2: return magnus::kRowLane;
+    case 3: return -32;
+    case 4: return -128;
+    case 5: return magnus::kWaveTile + 8;
+    case 6: return magnus::kWaveTile + 16;
+    default: return dim >= 65536 ? magnus::kWaveTile + 8 : 16;
+  }
+}
+
+int rows_per_block(magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  if (ctx->csr_variant) return variant_rows(ctx->csr_variant, h->H1.dim);
+  auto it = ctx->tuned_variant.find({(const void*)h->H1.row_ptr, h->H1.dim});
+  return variant_rows(it == ctx->tuned_variant.end() ? 0 : it->second, h->H1.dim);
 }
 
 hipEvent_t next_event(magnus_ctx* ctx) {
@@ -307,7 +323,7 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
   }
   CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
   CsrDev t2{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
-  const int rpb = rows_per_block(ctx, dim);
+  const int rpb = rows_per_block(ctx, h);
   if (op.kappa == 0.0) {
     a.x1 = win;
     a.x2 = win;
@@ -672,17 +688,20 @@ int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E
 }
 
 // Largest supported group size for the remaining states.
-int group_size(int remaining) {
+int group_size(int remaining, int cap = 32) {
   for (int g : {32, 16, 8, 4, 2})
-    if (remaining >= g) return g;
+    if (g <= cap && remaining >= g) return g;
   return 1;
 }
 
 bool multi_ok(const magnus_hamiltonian* h, double kappa) { return kappa == 0.0; }
 
-// Dense groups take every remaining state at once; CSR groups 32, 16, 8, 4, 2.
-int group_for(const magnus_hamiltonian* h, int remaining) {
-  return h->H1.format == MAGNUS_DENSE ? (remaining > 1 ? remaining : 1) : group_size(remaining);
+// Dense groups take every remaining state at once; CSR groups 32, 16, 8, 4, 2
+// (at most the autotuned group size).
+int group_for(magnus_ctx* ctx, const magnus_hamiltonian* h, int remaining) {
+  if (h->H1.format == MAGNUS_DENSE) return remaining > 1 ? remaining : 1;
+  auto it = ctx->tuned_group.find({(const void*)h->H1.row_ptr, h->H1.dim});
+  return group_size(remaining, it == ctx->tuned_group.end() ? 32 : it->second);
 }
 
 // Plan one group exponential, assembling the dense exponent when all states share it.
@@ -1056,6 +1075,104 @@ int magnus_dense_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_strea
   return MAGNUS_OK;
 }
 
+int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch, int32_t* variant,
+                    int32_t* group, double* variant_us, double* group_us, magnus_stream stream) {
+  int rc = check_ham(ctx, h, 0);
+  if (rc) return rc;
+  if ((rc = check_batch(ctx, batch))) return rc;
+  if (h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "magnus_autotune tunes CSR kernels");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = begin_call(ctx, s))) return rc;
+  if ((rc = ensure_valid(ctx, h, s))) return rc;
+  const int dim = (int)h->H1.dim;
+  const size_t nvec = (size_t)ctx->max_dim * (size_t)ctx->max_batch;
+  for (int k : {kA, kB, kS0, kY})
+    HIP_TRY(hipMemsetAsync(ctx->vec(k), 0, sizeof(double2) * nvec, s));
+  CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
+  CsrDev t2{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  constexpr int kReps = 5;
+  // time f (kReps launches after one untimed launch), in microseconds per launch
+  auto time_us = [&](auto f, double* us) -> hipError_t {
+    hipError_t e = f();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < kReps && e == hipSuccess; ++r) e = f();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    *us = 1e3 * (double)ms / kReps;
+    return e;
+  };
+  hipError_t err = hipSuccess;
+  // the single-state iteration: each row mapping on this matrix
+  IterArgs a{};
+  a.x1 = a.x2 = a.wcur = ctx->vec(kA);
+  a.wout = ctx->vec(kB);
+  a.pacc = ctx->vec(kS0);
+  a.slot = ctx->slots;
+  a.partials = ctx->partials;
+  a.a1 = a.a2 = 1.0;
+  a.first = 1;
+  double best = INFINITY;
+  int best_code = 0;
+  for (int code = 1; code <= kTuneVariants && err == hipSuccess; ++code) {
+    const int rpb = variant_rows(code, dim);
+    double us = 0.0;
+    err = time_us([&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }, &us);
+    if (variant_us) variant_us[code - 1] = us;
+    if (us < best) {
+      best = us;
+      best_code = code;
+    }
+  }
+  // the multi-state iteration: cost per state of each group size up to the batch
+  int best_group = 32;
+  double best_per_state = INFINITY;
+  std::vector<ColParam> table(32);
+  for (ColParam& c : table) c.a1 = c.a2 = 1.0;
+  if (err == hipSuccess && batch > 1) {
+    if ((rc = upload_table(ctx, table, s))) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+  }
+  int gi = 0;
+  for (int g : {2, 4, 8, 16, 32}) {
+    double us = NAN;
+    if (err == hipSuccess && g <= batch && (size_t)magnus::csr2_multi_grid(dim, g) * g * 2 <= ctx->npartials) {
+      MultiArgs m{};
+      m.x = ctx->vec(kY);
+      m.wout = ctx->vec(kA);
+      m.pacc = ctx->vec(kB);
+      m.slots = ctx->slots;
+      m.partials = ctx->partials;
+      m.prm = ctx->table;
+      m.B = g;
+      m.first = 1;
+      err = time_us([&] { return magnus::launch_csr2_multi(magnus::kMultiLeja, t1, t2, dim, m, s); }, &us);
+      if (err == hipSuccess && us / g < best_per_state) {
+        best_per_state = us / g;
+        best_group = g;
+      }
+    }
+    if (group_us) group_us[gi] = us;
+    ++gi;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(MAGNUS_EHIP, "autotune: %s", hipGetErrorString(err));
+  const auto key = std::make_pair((const void*)h->H1.row_ptr, h->H1.dim);
+  ctx->tuned_variant[key] = best_code;
+  if (batch > 1) ctx->tuned_group[key] = best_group;
+  if (variant) *variant = best_code;
+  if (group) *group = batch > 1 ? best_group : 1;
+  return MAGNUS_OK;
+}
+
 int magnus_destroy(magnus_ctx* ctx) {
   if (!ctx) return MAGNUS_OK;
   (void)hipSetDevice(ctx->device);
@@ -1135,7 +1252,7 @@ int expmv_leja(magnus_ctx* ctx, const magnus_hamiltonian* h, double a, double b,
   const double2* vin = reinterpret_cast<const double2*>(v);
   double2* wout = reinterpret_cast<double2*>(w);
   for (int32_t c = 0; c < batch;) {
-    const int g = (multi_ok(h, kappa) && tau != 0.0) ? group_for(h, batch - c) : 1;
+    const int g = (multi_ok(h, kappa) && tau != 0.0) ? group_for(ctx, h, batch - c) : 1;
     if (g > 1) {
       std::vector<double> av(g, a), bv(g, b);
       rc = multi_expmv_group(ctx, h, g, av.data(), bv.data(), tau, vin + c * dim, wout + c * dim, tol_e, opts, &acc, s);
@@ -1171,7 +1288,7 @@ static int step_common(int method, magnus_ctx* ctx, const magnus_hamiltonian* h,
   const double2* in = reinterpret_cast<const double2*>(psi_in);
   double2* out = reinterpret_cast<double2*>(psi_out);
   for (int32_t c = 0; c < batch;) {
-    const int g = (!S.commutator && multi_ok(h, 0.0)) ? group_for(h, batch - c) : 1;
+    const int g = (!S.commutator && multi_ok(h, 0.0)) ? group_for(ctx, h, batch - c) : 1;
     if (g > 1) {
       HIP_TRY(magnus::launch_pack(in + c * dim, ctx->vec(kY), (int)dim, g, s));
       rc = multi_cf_steps(ctx, h, S, g, tau, 0, 1, [&](int, int64_t, int j) { return fv[j]; }, tol_e, opts, &acc, s);
@@ -1255,7 +1372,7 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
       if (rc) return rc;
     }
     for (int32_t c = small ? batch : 0; c < batch;) {
-      const int g = grouped ? group_for(h, batch - c) : 1;
+      const int g = grouped ? group_for(ctx, h, batch - c) : 1;
       if (g > 1) {
         HIP_TRY(magnus::launch_pack(st + c * dim, ctx->vec(kY), (int)dim, g, s));
         rc = multi_cf_steps(ctx, h, S, g, tau, n, stop,

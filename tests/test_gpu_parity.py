@@ -465,3 +465,34 @@ def test_ragged_batch_matches_oracle():
             assert rel(out[k], ref) <= BUDGET
     assert st["exponentials"] == 2 * nsteps * (3 + 2 + 4 + 2)
     c.close()
+
+
+def test_autotune_choices_are_used_and_match_oracle():
+    """The autotuner times every CSR row mapping and multi-state group size on the
+    n = 13 chain, keeps the fastest, and later calls with those kernels still match
+    the oracle (single state and a group of 6)."""
+    n, tau, nsteps = 13, 0.01, 6
+    H1, H2 = chain(n)
+    c = B.Context(max_dim=1 << n, max_batch=6)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    res = B.magnus_autotune(c, ham, batch=6)
+    assert res["variant"] in B.CSR_VARIANTS
+    assert all(v > 0 for v in res["variant_us"].values())
+    assert res["group"] in (2, 4)
+    assert res["group_us"]["8"] is None and res["group_us"]["2"] > 0
+    f = inputs.cos_field(2.0)
+    fn = _field_nodes("CF4", f, 0.0, tau, nsteps)
+    psi0 = inputs.random_states(1 << n, seed=77, batch=6)
+    psi = dev(psi0)
+    B.propagate(c, ham, B.CF4, tau, fn, psi, opts=B.leja_opts(BUDGET, tol_mode=1))
+    out = host(psi)
+    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), f)
+    for k in (0, 5):
+        assert rel(out[k], mg.propagate("CF4", P, tau, nsteps, psi0[k], expm="taylor")) <= BUDGET
+    one = dev(psi0[2])
+    B.propagate(c, ham, B.CF4, tau, fn, one, opts=B.leja_opts(BUDGET, tol_mode=1))
+    assert rel(host(one), mg.propagate("CF4", P, tau, nsteps, psi0[2], expm="taylor")) <= BUDGET
+    with pytest.raises(B.MagnusError):
+        B.magnus_autotune(c, B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(
+            inputs.powerlaw_hermitian(64, 1.5, 1), inputs.powerlaw_hermitian(64, 1.5, 2))))
+    c.close()
