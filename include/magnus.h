@@ -71,7 +71,8 @@ typedef void* magnus_stream;   /* hipStream_t */
  * One Hermitian term of the Hamiltonian.
  *   format  MAGNUS_CSR: row_ptr[dim+1] (row_ptr[0] = 0, non-decreasing,
  *           row_ptr[dim] = nnz), col_idx[nnz] (0 <= col < dim), val[nnz]
- *           complex128.  Section 3 fixes CSR as the sparse format.
+ *           complex128 (both may be NULL when nnz = 0; rows may be empty).
+ *           Section 3 fixes CSR as the sparse format.
  *           MAGNUS_DENSE: val is a row-major dim x dim complex128 matrix with
  *           row stride ld >= dim elements (element (i, j) at val[i*ld + j]),
  *           the same ld for H1 and H2;

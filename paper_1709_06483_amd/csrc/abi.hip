@@ -119,11 +119,13 @@ int check_term(const magnus_term& t, int64_t dim, const char* name) {
   if (t.format != MAGNUS_CSR && t.format != MAGNUS_DENSE)
     return fail(MAGNUS_EINVAL, "%s: unknown format %d", name, t.format);
   if (t.dim != dim) return fail(MAGNUS_EINVAL, "%s: dim %lld != %lld", name, (long long)t.dim, (long long)dim);
-  if (!t.val) return fail(MAGNUS_EINVAL, "%s: null val", name);
   if (t.format == MAGNUS_CSR) {
-    if (!t.row_ptr || !t.col_idx) return fail(MAGNUS_EINVAL, "%s: null CSR index array", name);
     if (t.nnz < 0 || t.nnz > INT32_MAX) return fail(MAGNUS_EINVAL, "%s: nnz %lld out of range", name, (long long)t.nnz);
+    // a term without entries (the zero matrix) may pass null column and value arrays
+    if (!t.row_ptr || (t.nnz > 0 && (!t.col_idx || !t.val)))
+      return fail(MAGNUS_EINVAL, "%s: null CSR array", name);
   } else {
+    if (!t.val) return fail(MAGNUS_EINVAL, "%s: null val", name);
     if (t.ld < dim) return fail(MAGNUS_EINVAL, "%s: ld %lld < dim", name, (long long)t.ld);
   }
   if (!is_fin(t.lam_min) || !is_fin(t.lam_max) || t.lam_min > t.lam_max)

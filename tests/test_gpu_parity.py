@@ -496,3 +496,51 @@ def test_autotune_choices_are_used_and_match_oracle():
         B.magnus_autotune(c, B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(
             inputs.powerlaw_hermitian(64, 1.5, 1), inputs.powerlaw_hermitian(64, 1.5, 2))))
     c.close()
+
+
+def _tiny_hermitian(N, seed, density=0.5, empty_rows=()):
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    A = np.zeros((N, N), complex)
+    for i in range(N):
+        for j in range(i, N):
+            if rng.random() < density:
+                A[i, j] = rng.standard_normal() + (1j * rng.standard_normal() if i != j else 0.0)
+    A = A + np.triu(A, 1).conj().T
+    for r in empty_rows:
+        A[r, :] = 0.0
+        A[:, r] = 0.0
+    return inputs.CSR.from_scipy(sp.csr_matrix(A)), A
+
+
+@pytest.mark.parametrize("persist", ["1", "0"])
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 17, 130])
+def test_tiny_dims_empty_rows_and_zero_term(N, persist, monkeypatch):
+    """Degenerate inputs on every path: dimensions 1..130, rows without entries, and an
+    H2 with no entries at all (null column and value arrays); single states (small-state
+    kernel or per-iteration launches), a group of 3, and M4."""
+    import scipy.sparse as sp
+    monkeypatch.setenv("MAGNUS_PERSIST", persist)
+    H1, A1 = _tiny_hermitian(N, seed=900 + N, empty_rows=(N // 2,) if N > 2 else ())
+    H2z = inputs.CSR(np.zeros(N + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, complex), N)
+    H2, A2 = _tiny_hermitian(N, seed=950 + N, density=0.3)
+    c = B.Context(max_dim=N, max_batch=3)
+    tau, nsteps = 0.05, 7
+    f = inputs.cos_field(2.0)
+    psi0 = inputs.random_states(N, seed=960 + N, batch=3)
+    for second, A2d in ((H2z, np.zeros((N, N))), (H2, A2)):
+        ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, second))
+        P = mg.two_term(A1, A2d, f)
+        for method in ("CF4", "M4"):
+            fn = _field_nodes(method, f, 0.0, tau, nsteps)
+            one = dev(psi0[0])
+            B.propagate(c, ham, B.METHODS[method], tau, fn, one, opts=B.leja_opts(BUDGET, tol_mode=1))
+            ref = mg.propagate(method, P, tau, nsteps, psi0[0], expm="eig")
+            assert rel(host(one), ref) <= BUDGET, (method, N)
+        grp = dev(psi0)
+        B.propagate(c, ham, B.CF4, tau, _field_nodes("CF4", f, 0.0, tau, nsteps), grp,
+                    opts=B.leja_opts(BUDGET, tol_mode=1))
+        out = host(grp)
+        for k in range(3):
+            assert rel(out[k], mg.propagate("CF4", P, tau, nsteps, psi0[k], expm="eig")) <= BUDGET, (k, N)
+    c.close()
