@@ -61,6 +61,13 @@ __device__ __forceinline__ void leja_row(const IterArgs& a, int r, d2 y, double&
   pw += nrm2(wn);
 }
 
+// |w_i|^2 of the workgroup at partials[blockIdx.x]; on a substep's first
+// iteration also |v|^2 at partials[gridDim.x + blockIdx.x].
+__device__ __forceinline__ void store_partials(const IterArgs& a, double bw, double bv) {
+  a.partials[blockIdx.x] = bw;
+  if (a.first) a.partials[gridDim.x + blockIdx.x] = bv;
+}
+
 // Block sums of the norm partials, one pair per workgroup (plain stores: the
 // reduction across workgroups happens in leja_decide_kernel, after this
 // kernel has finished, so no device-scope atomics or fences are needed).
@@ -74,8 +81,7 @@ __device__ void block_partials(const IterArgs& a, double pw, double pv) {
   if (tid == 0) {
     double bw = 0.0, bv = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) { bw += red[0][w]; bv += red[1][w]; }
-    a.partials[2 * blockIdx.x] = bw;
-    a.partials[2 * blockIdx.x + 1] = bv;
+    store_partials(a, bw, bv);
   }
 }
 
@@ -85,23 +91,30 @@ __device__ void block_partials(const IterArgs& a, double pw, double pv) {
 // all of its loads before summing, so the kernel costs about one memory
 // round trip.
 constexpr int kDecideThreads = 1024;
-constexpr int kDecidePer = 16;
+constexpr int kDecidePer = 32;
+// sum of p[0..n) over the workgroup's threads (each thread's loads all issued first)
+__device__ __forceinline__ double decide_sum(const double* p, int n, int tid) {
+  double s = 0.0;
+  for (int k0 = 0; k0 < n; k0 += kDecideThreads * kDecidePer) {
+    double v[kDecidePer];
+#pragma unroll
+    for (int u = 0; u < kDecidePer; ++u) {
+      const int k = k0 + u * kDecideThreads + tid;
+      v[u] = k < n ? p[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kDecidePer; ++u) s += v[u];
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(kDecideThreads) void leja_decide_kernel(IterArgs a, int grid) {
   __shared__ double red[2][kDecideThreads / 64];
   if (a.check_stop && load_stopped(a.slot)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const d2* P = reinterpret_cast<const d2*>(a.partials);
-  double sw = 0.0, sv = 0.0;
-  for (int k0 = 0; k0 < grid; k0 += kDecideThreads * kDecidePer) {
-    d2 v[kDecidePer];
-#pragma unroll
-    for (int u = 0; u < kDecidePer; ++u) {
-      const int k = k0 + u * kDecideThreads + tid;
-      v[u] = k < grid ? P[k] : d2{0.0, 0.0};
-    }
-#pragma unroll
-    for (int u = 0; u < kDecidePer; ++u) { sw += v[u].x; sv += v[u].y; }
-  }
+  // |v|^2 partials exist (and matter) only on a substep's first iteration
+  double sw = decide_sum(a.partials, grid, tid);
+  double sv = a.first ? decide_sum(a.partials + grid, grid, tid) : 0.0;
   sw = wave_sum(sw);
   sv = wave_sum(sv);
   if (lane == 0) { red[0][wv] = sw; red[1][wv] = sv; }
@@ -372,8 +385,7 @@ __global__ __launch_bounds__(kThreads) void csr2_rowlane_kernel(CsrDev t1, CsrDe
     if (tid == 0) {
       double bw = 0.0, bv = 0.0;
       for (int k = 0; k < kThreads / 64; ++k) { bw += wred[0][k]; bv += wred[1][k]; }
-      a.partials[2 * blockIdx.x] = bw;
-      a.partials[2 * blockIdx.x + 1] = bv;
+      store_partials(a, bw, bv);
     }
   }
 }
@@ -544,8 +556,7 @@ __global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave
     if (tid == 0) {
       double bw = 0.0, bv = 0.0;
       for (int k = 0; k < NWAVE; ++k) { bw += wred[0][k]; bv += wred[1][k]; }
-      a.partials[2 * blockIdx.x] = bw;
-      a.partials[2 * blockIdx.x + 1] = bv;
+      store_partials(a, bw, bv);
     }
   }
 }
