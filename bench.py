@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--workload", default="chain_n20",
                     choices=["chain_n20", "chain_n10", "dense_8192", "batched_dense_4096", "ragged_chains",
-                             "adjoint_chain_n16"],
+                             "adjoint_chain_n16", "adjoint_dense_4096"],
                     help="chain_n20 is the headline line; the others print one informational line each")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size heuristic for the CSR kernel")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -402,16 +402,25 @@ def other_workload(name: str, args):
         line.update({"metric": "ragged batch Cf4 Magnus steps/sec (4 sizes x 16 instances)",
                      "value": K / (ms * 1e-3), "unit": "steps/s", "steps": K, "ms_per_step": ms / K,
                      "instance_steps_per_s": len(sizes) * per * K / (ms * 1e-3)})
-    elif name == "adjoint_chain_n16":
+    elif name in ("adjoint_chain_n16", "adjoint_dense_4096"):
         from paper_1709_06483_amd import adjoint as A
-        n, P, T, nsteps = 16, 32, 2.0, 400
+        P, T, nsteps = 32, 2.0, 400
         tau = T / nsteps
-        H1, H2 = inputs.chain_terms(n)
-        ctx = B.Context(max_dim=1 << n, max_batch=2)
-        ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+        if name == "adjoint_chain_n16":
+            dim = 1 << 16
+            H1, H2 = inputs.chain_terms(16)
+            ctx = B.Context(max_dim=dim, max_batch=2)
+            ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+            what = "n=16 chain"
+        else:
+            dim = 4096
+            ctx = B.Context(max_dim=dim, max_batch=2)
+            ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(
+                inputs.powerlaw_hermitian(dim, 1.5, 20), inputs.powerlaw_hermitian(dim, 1.5, 21)))
+            what = "dense 4096"
         theta = inputs.fourier_theta(P, 40)
-        d0 = torch.from_numpy(inputs.random_states(1 << n, seed=41)).cuda()
-        dt = torch.from_numpy(inputs.random_states(1 << n, seed=42)).cuda()
+        d0 = torch.from_numpy(inputs.random_states(dim, seed=41)).cuda()
+        dt = torch.from_numpy(inputs.random_states(dim, seed=42)).cuda()
         prob = A.ControlProblem.with_basis(ctx, ham, tau, nsteps, inputs.fourier_basis(P, T), d0, dt, every_k=20,
                                            opts=B.leja_opts(1e-10 / (2 * nsteps)))
         prob.loss_and_grad(theta)
@@ -419,7 +428,7 @@ def other_workload(name: str, args):
         f = prob.basis_nodes @ theta
         psi = d0.clone()
         ms_f, _ = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, f, psi, opts=prob.opts))
-        line.update({"metric": "adjoint loss+gradient time vs forward (n=16 chain, 400 Cf4 steps, 32 params)",
+        line.update({"metric": f"adjoint loss+gradient time vs forward ({what}, 400 Cf4 steps, 32 params)",
                      "value": ms_g / ms_f, "unit": "ratio", "gradient_ms": ms_g, "forward_ms": ms_f,
                      "loss": loss, "grad_norm": float(np.linalg.norm(grad))})
     print(json.dumps(line), flush=True)
