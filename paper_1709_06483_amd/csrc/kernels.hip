@@ -582,15 +582,22 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
   for (int r = 0; r < RPW; ++r) { acc1[r] = d2{0.0, 0.0}; acc2[r] = d2{0.0, 0.0}; }
   int nr = min(RPW, dim - rbase);
   if (nr < 0) nr = 0;
-#pragma unroll 2
-  for (int j = lane; j < dim; j += 64) {
-    const d2 xj = x[j];
+  // columns in groups of UNR per lane: the same matrix bytes in flight per wave for one term or two
+  constexpr int UNR = NT == 2 ? 2 : 4;
+  for (int j0 = lane; j0 < dim; j0 += 64 * UNR) {
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      if (r < nr) {
-        const long long off = (long long)(rbase + r) * ld + j;
-        acc1[r] += cmul(__builtin_nontemporal_load(A1 + off), xj);
-        if constexpr (NT == 2) acc2[r] += cmul(__builtin_nontemporal_load(A2 + off), xj);
+    for (int u = 0; u < UNR; ++u) {
+      const int j = j0 + 64 * u;
+      if (j < dim) {
+        const d2 xj = x[j];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          if (r < nr) {
+            const long long off = (long long)(rbase + r) * ld + j;
+            acc1[r] += cmul(__builtin_nontemporal_load(A1 + off), xj);
+            if constexpr (NT == 2) acc2[r] += cmul(__builtin_nontemporal_load(A2 + off), xj);
+          }
+        }
       }
     }
   }

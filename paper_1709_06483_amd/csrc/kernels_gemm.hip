@@ -118,15 +118,14 @@ __global__ __launch_bounds__(256) void commutator_combine_kernel(const double2* 
 
 // out = sum_t c_t M_t (out row stride n).
 __global__ __launch_bounds__(kThreads) void assemble_terms_kernel(AssembleTerms T, int n, double2* __restrict__ out) {
-  const long long total = (long long)n * n;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long r = i / n, c = i % n;
-    d2 h = {0.0, 0.0};
-    for (int t = 0; t < T.nterms; ++t)
-      h += rmul(T.c[t], __builtin_nontemporal_load(reinterpret_cast<const d2*>(T.m[t]) + r * T.ld[t] + c));
-    out[i] = fromd2(h);
-  }
+  // rows over the grid, columns over the threads (no index division)
+  for (long long r = blockIdx.x; r < n; r += gridDim.x)
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      d2 h = {0.0, 0.0};
+      for (int t = 0; t < T.nterms; ++t)
+        h += rmul(T.c[t], __builtin_nontemporal_load(reinterpret_cast<const d2*>(T.m[t]) + r * T.ld[t] + c));
+      out[r * n + c] = fromd2(h);
+    }
 }
 
 }  // namespace

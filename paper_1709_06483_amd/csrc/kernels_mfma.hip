@@ -187,14 +187,16 @@ template <bool WITH_K>
 __global__ void dense_assemble_kernel(const double2* __restrict__ H1, const double2* __restrict__ H2, long long ld,
                                       int dim, double ca, double cb, const double2* __restrict__ K, double ck,
                                       double2* __restrict__ out) {
-  const long long n = (long long)dim * dim;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const long long r = i / dim, c = i % dim;
-    const d2 x = __builtin_nontemporal_load(reinterpret_cast<const d2*>(H1) + r * ld + c);
-    const d2 y = __builtin_nontemporal_load(reinterpret_cast<const d2*>(H2) + r * ld + c);
-    d2 h = rmul(ca, x) + rmul(cb, y);
-    if constexpr (WITH_K) h += rmul(ck, __builtin_nontemporal_load(reinterpret_cast<const d2*>(K) + i));
-    out[i] = fromd2(h);
+  // rows over the grid, columns over the threads (no index division)
+  for (long long r = blockIdx.x; r < dim; r += gridDim.x) {
+    const d2* h1 = reinterpret_cast<const d2*>(H1) + r * ld;
+    const d2* h2 = reinterpret_cast<const d2*>(H2) + r * ld;
+    double2* o = out + r * dim;
+    for (int c = threadIdx.x; c < dim; c += blockDim.x) {
+      d2 h = rmul(ca, __builtin_nontemporal_load(h1 + c)) + rmul(cb, __builtin_nontemporal_load(h2 + c));
+      if constexpr (WITH_K) h += rmul(ck, __builtin_nontemporal_load(reinterpret_cast<const d2*>(K) + r * dim + c));
+      o[c] = fromd2(h);
+    }
   }
 }
 
