@@ -114,14 +114,24 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const double hre = sHre[t][ar][kk], him = sHim[t][ar][kk];
+        double wre[TJ], wim[TJ];
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj) {
           const int bc = wc * WN + tj * 16 + (lane & 15);
-          const double wre = sWre[kk][bc] * sc[t][tj], wim = sWim[kk][bc] * sc[t][tj];
-          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wre, are[tj], 0, 0, 0);
-          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-him, wim, are[tj], 0, 0, 0);
-          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wim, aim[tj], 0, 0, 0);
-          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(him, wre, aim[tj], 0, 0, 0);
+          wre[tj] = sWre[kk][bc] * sc[t][tj];
+          wim[tj] = sWim[kk][bc] * sc[t][tj];
+        }
+        // the 2 TJ accumulators are independent chains: issue one product into each
+        // before the second product of any, so dependent MFMAs are never back to back
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wre[tj], are[tj], 0, 0, 0);
+          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wim[tj], aim[tj], 0, 0, 0);
+        }
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-him, wim[tj], are[tj], 0, 0, 0);
+          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(him, wre[tj], aim[tj], 0, 0, 0);
         }
       }
     }
