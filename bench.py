@@ -374,6 +374,11 @@ def other_workload(name: str, args):
         kms, kn = ctx.timing_read(B.KERNEL_DENSE_MFMA)
         ctx.timing(False)
         flops = 8.0 * N * N * Bn * kn
+        # plain: the same steps for one state at a time (GEMV iterations), as state-steps/s
+        one = psi[0].clone()
+        ms1, _ = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, fn[W:], one, opts=B.leja_opts(tol_e)))
+        line["plain_state_steps_per_s"] = K / (ms1 * 1e-3)
+        line["batched_vs_plain"] = (Bn * K / (ms * 1e-3)) / (K / (ms1 * 1e-3))
         line.update({"metric": "batched Cf4 Magnus steps/sec (256 states)", "value": K / (ms * 1e-3),
                      "unit": "steps/s", "steps": K, "ms_per_step": ms / K, "state_steps_per_s": Bn * K / (ms * 1e-3),
                      "gemm_launches": kn, "gemm_avg_us": 1e3 * kms / max(kn, 1),
@@ -399,6 +404,11 @@ def other_workload(name: str, args):
         if W:
             B.magnus_propagate_ragged(ctx, warm, B.CF4, tau, opts=B.leja_opts(tol_e))
         ms, _ = _timed(lambda: B.magnus_propagate_ragged(ctx, timed, B.CF4, tau, opts=B.leja_opts(tol_e)))
+        # plain: every instance propagated on its own, one call per state
+        plain = [(ham, psi[k].clone(), fn[k, W:]) for ham, psi, fn in probs for k in range(psi.shape[0])]
+        ms1, _ = _timed(lambda: [B.propagate(ctx, h, B.CF4, tau, f, p, opts=B.leja_opts(tol_e)) for h, p, f in plain])
+        line["plain_instance_steps_per_s"] = len(plain) * K / (ms1 * 1e-3)
+        line["batched_vs_plain"] = ms1 / ms
         line.update({"metric": "ragged batch Cf4 Magnus steps/sec (4 sizes x 16 instances)",
                      "value": K / (ms * 1e-3), "unit": "steps/s", "steps": K, "ms_per_step": ms / K,
                      "instance_steps_per_s": len(sizes) * per * K / (ms * 1e-3)})

@@ -200,7 +200,11 @@ int magnus_check(magnus_ctx* ctx, magnus_stream stream);
 /* Fill h->H1.lam_min/lam_max, h->H2.lam_min/lam_max (Gershgorin discs, rigorous
  * for Hermitian terms) and h->k_min/k_max (|K| <= 2 |H1| |H2|).  Also validates
  * CSR structure (row_ptr monotone, row_ptr[0] = 0, row_ptr[dim] = nnz, columns
- * in range) and returns EINVAL if it is malformed.  Synchronous. */
+ * in range) and returns EINVAL if it is malformed.  Synchronous.
+ * Every call that takes CSR terms validates a term once per context (recognised
+ * by its three array pointers, dim and nnz) before any kernel gathers through
+ * it; a caller that rewrites a term's arrays in place calls this function
+ * again, which re-validates it (a failed re-validation leaves it invalid). */
 int magnus_spectral_bounds(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
 
 /* ---- the hot path ------------------------------------------------------------ */

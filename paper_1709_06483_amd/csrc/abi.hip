@@ -167,6 +167,12 @@ int csr_scan(magnus_ctx* ctx, const magnus_term& t, hipStream_t s, double* lo, d
   const int dim = (int)t.dim;
   const int grid = magnus::csr_gershgorin_grid(dim);
   if (3 * (int64_t)grid > ctx->scan_len) return fail(MAGNUS_ENOMEM, "scan buffer too small");
+  auto key = std::make_tuple((const void*)t.row_ptr, (const void*)t.col_idx, t.val, t.dim, t.nnz);
+  {
+    // a term scanned again (its arrays may have been rewritten) counts as valid only if this scan passes
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->validated.erase(key);
+  }
   double* dout = ctx->scan;
   CsrDev d{t.row_ptr, t.col_idx, reinterpret_cast<const double2*>(t.val)};
   hipError_t e = magnus::launch_csr_gershgorin(d, dim, t.nnz, dout, grid, s);
@@ -184,7 +190,6 @@ int csr_scan(magnus_ctx* ctx, const magnus_term& t, hipStream_t s, double* lo, d
   if (bad) return fail(MAGNUS_EINVAL, "malformed CSR (row_ptr not monotone / not 0..nnz, or column out of range)");
   *lo = a;
   *hi = b;
-  auto key = std::make_tuple((const void*)t.row_ptr, (const void*)t.col_idx, t.val, t.dim, t.nnz);
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->validated.insert(key);
   return MAGNUS_OK;

@@ -544,3 +544,23 @@ def test_tiny_dims_empty_rows_and_zero_term(N, persist, monkeypatch):
         for k in range(3):
             assert rel(out[k], mg.propagate("CF4", P, tau, nsteps, psi0[k], expm="eig")) <= BUDGET, (k, N)
     c.close()
+
+
+def test_term_rewritten_in_place_is_revalidated():
+    """A term validated once and then corrupted in place (a column out of range) is
+    caught when the caller re-scans it, and stays refused afterwards."""
+    H1, H2 = chain(7)
+    c = B.Context(max_dim=128, max_batch=1)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    psi = dev(inputs.random_states(128, seed=3))
+    B.expmv_leja(c, ham, 1.0, 0.5, 0.0, 0.05, psi)
+    ci = ham.tensors[1]  # H1's column indices on the device
+    ci[3] = 1000
+    torch.cuda.synchronize()
+    with pytest.raises(B.MagnusError) as e:
+        B.magnus_spectral_bounds(c, ham)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.MagnusError) as e:
+        B.expmv_leja(c, ham, 1.0, 0.5, 0.0, 0.05, psi)
+    assert e.value.code == B.EINVAL
+    c.close()
