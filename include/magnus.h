@@ -138,9 +138,13 @@ typedef struct {
 /* ---- context -------------------------------------------------------------- */
 
 /* Create a context on `device` owning a workspace for states of up to
- * max_dim entries and batches of up to max_batch states (the only device
- * allocation the library makes; about 8 vectors per state).  *out receives the
- * context.  Errors: EINVAL (null out, max_dim < 1, max_batch < 1),
+ * max_dim entries and batches of up to max_batch states (allocated here; later
+ * allocations happen only in magnus_reserve_dense, magnus_dense_commutator and
+ * magnus_dense_m6_prepare; about 8 vectors per state).  *out receives the
+ * context.  Calls on one context share its workspace: they must not run
+ * concurrently from several host threads, and work they enqueue on different
+ * streams must not overlap on the device (one stream per context, or the
+ * caller orders them).  Errors: EINVAL (null out, max_dim < 1, max_batch < 1),
  * EHIP (device or allocation failure). */
 int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t device);
 
