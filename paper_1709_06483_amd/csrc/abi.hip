@@ -959,6 +959,8 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   // the multi-state CSR kernel writes dim * B^2 / 128 doubles (B <= 32: at most 8 dim)
   c->npartials = 2 * (size_t)c->max_grid + 8 * (size_t)max_dim +
                  (size_t)max_dim * (size_t)std::max(1, max_batch) / 8 + (size_t)max_dim + 64;
+  // the dot-product kernel's per-workgroup pairs, whatever the dimension
+  c->npartials = std::max(c->npartials, (size_t)magnus::kDotPartials + 64);
   if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->npartials);
   if (e == hipSuccess) e = hipMalloc(&c->scan, sizeof(double) * (size_t)c->scan_len);
   if (e == hipSuccess) e = hipMemset(c->slots, 0, sizeof(Slot) * c->nslots);

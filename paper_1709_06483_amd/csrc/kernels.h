@@ -170,7 +170,8 @@ hipError_t launch_dense_frechet(const double2* H1, const double2* H2, int dim, l
                                 hipStream_t s);
 int dense_frechet_grid(int dim);
 
-// out = sum_i conj(x[i*sx]) y[i*sy] (fixed order; partials: 1024 doubles).
+// out = sum_i conj(x[i*sx]) y[i*sy] (fixed order; partials: kDotPartials doubles).
+constexpr int kDotPartials = 1024;
 hipError_t launch_cdot(const double2* x, long long sx, const double2* y, long long sy, long long n, double* partials,
                        double2* out, hipStream_t s);
 // dst (interleaved pair) = [0; v].

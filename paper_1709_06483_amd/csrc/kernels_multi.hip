@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void dense_frechet_kernel(const double2* 
 }
 
 // Fixed-order complex dot product sum_i conj(x_i) y_i (strided operands).
-constexpr int kDotBlocks = 512;
+constexpr int kDotBlocks = kDotPartials / 2;
 __global__ __launch_bounds__(kThreads) void cdot_partial_kernel(const double2* x, long long sx, const double2* y,
                                                                long long sy, long long n, double* partials) {
   __shared__ double red[2][kThreads / 64];
