@@ -59,6 +59,8 @@ def main():
                              "adjoint_chain_n16", "adjoint_dense_4096"],
                     help="chain_n20 is the headline line; the others print one informational line each")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size heuristic for the CSR kernel")
+    ap.add_argument("--bounds", choices=["gershgorin", "lanczos"], default="lanczos",
+                    help="spectral enclosures of the terms: rigorous Gershgorin discs or Lanczos estimates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -106,7 +108,12 @@ def main():
           file=sys.stderr, flush=True)
 
     ctx = B.Context(max_dim=dim)
-    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    if args.bounds == "lanczos":
+        ham = B.magnus_spectral_bounds_lanczos(ctx, B.DeviceHamiltonian.from_csr(H1, H2), steps=60, margin=0.01)
+    else:
+        ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    print(f"[bench] spectral enclosures ({args.bounds}): H1 [{ham.struct.H1.lam_min:.3f}, {ham.struct.H1.lam_max:.3f}], "
+          f"H2 [{ham.struct.H2.lam_min:.3f}, {ham.struct.H2.lam_max:.3f}]", file=sys.stderr, flush=True)
     tune = B.magnus_autotune(ctx, ham) if not args.no_autotune else None
     if tune:
         print(f"[bench] autotune: {tune['variant_name']} "
@@ -191,7 +198,7 @@ def main():
             "workload": "chain_n20: open XXZ chain J=1 Delta=0.5 + cos(2t) sum X_i, n=20 (dim 1048576), "
                         "complex128 CSR, Cf4, tau=0.01, 500-step run on [0,5], Leja budget 1e-10",
             "dim": dim, "nnz": nnz_total, "tau": tau, "method": "CF4",
-            "tol_per_exponential": tol_cf4, "early_termination": True,
+            "tol_per_exponential": tol_cf4, "early_termination": True, "spectral_bounds": args.bounds,
         },
         "hv_gbps": hv_gbps,
         "leja_iters_per_step": st["iters"] / K,

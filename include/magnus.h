@@ -211,6 +211,21 @@ int magnus_check(magnus_ctx* ctx, magnus_stream stream);
  * again, which re-validates it (a failed re-validation leaves it invalid). */
 int magnus_spectral_bounds(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
 
+/* Tighter spectral estimates by the Lanczos process (Section 3 needs only an
+ * estimate of the spectrum): first as magnus_spectral_bounds (which also
+ * validates), then `steps` Lanczos steps on each term from a fixed
+ * pseudo-random start vector (the term's products run on the device), and
+ * each term's enclosure becomes [theta_min - d, theta_max + d] intersected with
+ * its Gershgorin interval, theta_min/max the extreme Ritz values and
+ * d = max(margin (theta_max - theta_min), 3 x their change over the last 10
+ * steps); k_min/k_max = -+2 |H1| |H2| with the new norms.  Unlike the
+ * Gershgorin discs this is an estimate, not a proof: the a priori Leja error
+ * bound assumes the spectrum lies inside.  Uses the context's work vectors.
+ * Synchronous (one host wait per dot product).
+ * Errors: as magnus_spectral_bounds; EINVAL (steps < 2, margin < 0); ENAN. */
+int magnus_spectral_bounds_lanczos(magnus_ctx* ctx, magnus_hamiltonian* h, int32_t steps, double margin,
+                                   magnus_stream stream);
+
 /* ---- the hot path ------------------------------------------------------------ */
 
 /* w = exp(-i tau (a H1 + b H2 + kappa K)) v for `batch` states

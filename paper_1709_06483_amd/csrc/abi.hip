@@ -1240,6 +1240,126 @@ int magnus_spectral_bounds(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream
   return MAGNUS_OK;
 }
 
+namespace {
+
+// y = H x for one term (the iteration kernels with the other term empty or absent).
+int apply_term(magnus_ctx* ctx, const magnus_term& t, const double2* x, double2* y, hipStream_t s) {
+  const int dim = (int)t.dim;
+  IterArgs a{};
+  a.x1 = a.x2 = a.wcur = x;
+  a.wout = y;
+  a.pacc = ctx->vec(kS1);
+  a.slot = ctx->slots;
+  a.partials = ctx->partials;
+  a.a1 = 1.0;
+  a.first = 1;
+  if (t.format == MAGNUS_DENSE) {
+    HIP_TRY(magnus::launch_dense2_iter(reinterpret_cast<const double2*>(t.val), nullptr, dim, t.ld, a, s));
+    return MAGNUS_OK;
+  }
+  CsrDev t1{t.row_ptr, t.col_idx, reinterpret_cast<const double2*>(t.val)};
+  CsrDev none{reinterpret_cast<const int*>(ctx->vec(kV)), nullptr, nullptr};  // all rows empty
+  HIP_TRY(magnus::launch_csr2_iter(magnus::kLeja, t1, none, dim, a, variant_rows(0, dim), s));
+  return MAGNUS_OK;
+}
+
+// Re(x^H y) on the host (one device dot product and a wait).
+int dot_re(magnus_ctx* ctx, const double2* x, const double2* y, int64_t n, double* out, hipStream_t s) {
+  double2* dev_out = reinterpret_cast<double2*>(ctx->partials + magnus::kDotPartials);
+  HIP_TRY(magnus::launch_cdot(x, 1, y, 1, n, ctx->partials, dev_out, s));
+  double2 h;
+  HIP_TRY(hipMemcpyAsync(&h, dev_out, sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = h.x;
+  return MAGNUS_OK;
+}
+
+// Lanczos on one Hermitian term from a fixed pseudo-random start: extreme Ritz
+// values after `steps` steps and their change over the last steps.
+int lanczos_term(magnus_ctx* ctx, const magnus_term& t, int steps, double* lo, double* hi, double* drift,
+                 hipStream_t s) {
+  const int64_t n = t.dim;
+  double2* P = ctx->vec(kA);  // previous basis vector
+  double2* C = ctx->vec(kB);  // current basis vector
+  double2* W = ctx->vec(kS0);
+  HIP_TRY(hipMemsetAsync(ctx->vec(kV), 0, sizeof(int) * (size_t)(n + 1), s));
+  HIP_TRY(hipMemsetAsync(P, 0, sizeof(double2) * (size_t)n, s));
+  {
+    // start vector: splitmix64 stream mapped to [-1, 1)^2, normalised on the host
+    std::vector<double2> v0((size_t)n);
+    uint64_t z = 0x9E3779B97F4A7C15ull;
+    double nrm = 0.0;
+    auto next = [&z]() {
+      z += 0x9E3779B97F4A7C15ull;
+      uint64_t r = z;
+      r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+      r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+      r ^= r >> 31;
+      return (double)(r >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    };
+    for (auto& e : v0) {
+      e.x = next();
+      e.y = next();
+      nrm += e.x * e.x + e.y * e.y;
+    }
+    const double inv = 1.0 / std::sqrt(nrm);
+    for (auto& e : v0) {
+      e.x *= inv;
+      e.y *= inv;
+    }
+    HIP_TRY(hipMemcpyAsync(C, v0.data(), sizeof(double2) * v0.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  std::vector<double> al, be;
+  double beta_prev = 0.0, lo_prev = 0.0, hi_prev = 0.0;
+  *drift = 0.0;
+  const int k = (int)std::min<int64_t>(steps, n);
+  for (int j = 0; j < k; ++j) {
+    int rc = apply_term(ctx, t, C, W, s);
+    if (rc) return rc;
+    double alpha, beta2;
+    if ((rc = dot_re(ctx, C, W, n, &alpha, s))) return rc;
+    HIP_TRY(magnus::launch_lanczos_orth(W, C, P, alpha, beta_prev, n, s));
+    if ((rc = dot_re(ctx, W, W, n, &beta2, s))) return rc;
+    al.push_back(alpha);
+    const double beta = std::sqrt(std::max(beta2, 0.0));
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(MAGNUS_ENAN, "Lanczos met a non-finite value");
+    if (j + 1 == k || beta <= 1e-13 * (std::fabs(alpha) + 1.0)) break;  // done, or an invariant subspace
+    be.push_back(beta);
+    HIP_TRY(magnus::launch_scale(W, 1.0 / beta, P, n, s));  // P becomes the next vector
+    std::swap(P, C);
+    beta_prev = beta;
+    if (j + 1 == k - 10) magnus::tridiag_extremes(al, be, &lo_prev, &hi_prev);
+  }
+  be.resize(al.size() - 1);
+  magnus::tridiag_extremes(al, be, lo, hi);
+  if ((int)al.size() > 10) *drift = std::max(std::fabs(*lo - lo_prev), std::fabs(*hi - hi_prev));
+  return MAGNUS_OK;
+}
+
+}  // namespace
+
+int magnus_spectral_bounds_lanczos(magnus_ctx* ctx, magnus_hamiltonian* h, int32_t steps, double margin,
+                                   magnus_stream stream) {
+  int rc = magnus_spectral_bounds(ctx, h, stream);  // validates; the Gershgorin enclosures cap the estimate
+  if (rc) return rc;
+  if (steps < 2 || !(margin >= 0.0)) return fail(MAGNUS_EINVAL, "steps %d < 2 or margin %g < 0", steps, margin);
+  hipStream_t s = (hipStream_t)stream;
+  for (magnus_term* t : {&h->H1, &h->H2}) {
+    double lo, hi, drift;
+    if ((rc = lanczos_term(ctx, *t, steps, &lo, &hi, &drift, s))) return rc;
+    const double d = std::max(margin * (hi - lo), 3.0 * drift);
+    t->lam_min = std::max(t->lam_min, lo - d);
+    t->lam_max = std::min(t->lam_max, hi + d);
+    if (t->lam_min > t->lam_max) t->lam_min = t->lam_max = 0.5 * (lo + hi);
+  }
+  const double n1 = std::fmax(std::fabs(h->H1.lam_min), std::fabs(h->H1.lam_max));
+  const double n2 = std::fmax(std::fabs(h->H2.lam_min), std::fabs(h->H2.lam_max));
+  h->k_min = -2.0 * n1 * n2;
+  h->k_max = 2.0 * n1 * n2;
+  return MAGNUS_OK;
+}
+
 int expmv_leja(magnus_ctx* ctx, const magnus_hamiltonian* h, double a, double b, double kappa, double tau,
                const void* v, void* w, int32_t batch, const magnus_leja_opts* opts, magnus_stats* stats,
                magnus_stream stream) {

@@ -174,6 +174,10 @@ int dense_frechet_grid(int dim);
 constexpr int kDotPartials = 1024;
 hipError_t launch_cdot(const double2* x, long long sx, const double2* y, long long sy, long long n, double* partials,
                        double2* out, hipStream_t s);
+// Lanczos helpers: w <- w - alpha v - beta u; y = sc x.
+hipError_t launch_lanczos_orth(double2* w, const double2* v, const double2* u, double alpha, double beta, long long n,
+                               hipStream_t s);
+hipError_t launch_scale(const double2* x, double sc, double2* y, long long n, hipStream_t s);
 // dst (interleaved pair) = [0; v].
 hipError_t launch_frechet_init(const double2* v, double2* dst, int dim, hipStream_t s);
 

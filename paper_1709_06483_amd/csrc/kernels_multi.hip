@@ -8,6 +8,8 @@
 // coupling term runs the Leja recurrence on the block vector of
 // [[H, H2], [0, H]], whose exponential carries the Frechet derivative of the
 // matrix exponential in its upper-right block.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace magnus {
@@ -346,6 +348,18 @@ __global__ __launch_bounds__(kThreads) void cdot_final_kernel(const double* part
   }
 }
 
+// One Lanczos orthogonalisation: w <- w - alpha v - beta u (w holds H v on entry).
+__global__ void lanczos_orth_kernel(double2* __restrict__ w, const double2* __restrict__ v,
+                                    const double2* __restrict__ u, double alpha, double beta, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    w[i] = fromd2(tod2(w[i]) - rmul(alpha, tod2(v[i])) - rmul(beta, tod2(u[i])));
+}
+
+__global__ void scale_kernel(const double2* __restrict__ x, double sc, double2* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = fromd2(rmul(sc, tod2(x[i])));
+}
+
 // Block vector [0; v] of the Frechet exponential, interleaved (element (row, b) at 2 row + b).
 __global__ void frechet_init_kernel(const double2* __restrict__ v, double2* __restrict__ dst, int dim) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -411,6 +425,19 @@ hipError_t launch_dense_frechet(const double2* H1, const double2* H2, int dim, l
                                 hipStream_t s) {
   if (a.B != 2) return hipErrorInvalidValue;
   dense_frechet_kernel<kFrechetRPW><<<dense_frechet_grid(dim), kThreads, 0, s>>>(H1, H2, dim, ld, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_orth(double2* w, const double2* v, const double2* u, double alpha, double beta, long long n,
+                               hipStream_t s) {
+  const long long g = std::min<long long>((n + kThreads - 1) / kThreads, 4096);
+  lanczos_orth_kernel<<<(unsigned)std::max<long long>(g, 1), kThreads, 0, s>>>(w, v, u, alpha, beta, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double2* x, double sc, double2* y, long long n, hipStream_t s) {
+  const long long g = std::min<long long>((n + kThreads - 1) / kThreads, 4096);
+  scale_kernel<<<(unsigned)std::max<long long>(g, 1), kThreads, 0, s>>>(x, sc, y, n);
   return hipGetLastError();
 }
 

@@ -418,4 +418,40 @@ bool method_scheme(int method, Scheme* out) {
   return true;
 }
 
+namespace {
+// Eigenvalues of the tridiagonal matrix below x (signs of the LDL^T pivots).
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int count = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double off = i ? b[i - 1] * b[i - 1] : 0.0;
+    q = a[i] - x - (i ? off / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++count;
+  }
+  return count;
+}
+}  // namespace
+
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double* lo, double* hi) {
+  const size_t k = a.size();
+  double g_lo = INFINITY, g_hi = -INFINITY;  // Gershgorin interval of the tridiagonal
+  for (size_t i = 0; i < k; ++i) {
+    const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    g_lo = std::min(g_lo, a[i] - r);
+    g_hi = std::max(g_hi, a[i] + r);
+  }
+  auto bisect = [&](int target) {  // smallest x with count(x) >= target
+    double l = g_lo - 1.0, h = g_hi + 1.0;
+    for (int it = 0; it < 200 && h - l > 1e-15 * std::max(1.0, std::fabs(h)); ++it) {
+      const double m = 0.5 * (l + h);
+      if (sturm_count(a, b, m) >= target) h = m;
+      else l = m;
+    }
+    return h;
+  };
+  *lo = bisect(1);
+  *hi = bisect((int)k);
+}
+
 }  // namespace magnus

@@ -113,4 +113,8 @@ struct Scheme {
 // Method ids as in the public header: 0 Cf4, 1 M4, 2 M2, 3 Cf4:3, 4 M6.
 bool method_scheme(int method, Scheme* out);
 
+// Smallest and largest eigenvalue of the symmetric tridiagonal matrix with
+// diagonal a[0..k) and off-diagonal b[0..k-1) (Sturm-sequence bisection).
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double* lo, double* hi);
+
 }  // namespace magnus

@@ -564,3 +564,57 @@ def test_term_rewritten_in_place_is_revalidated():
         B.expmv_leja(c, ham, 1.0, 0.5, 0.0, 0.05, psi)
     assert e.value.code == B.EINVAL
     c.close()
+
+
+@pytest.mark.parametrize("kind", ["chain", "dense"])
+def test_lanczos_bounds_enclose_the_spectrum_and_tighten(kind):
+    """The Lanczos estimates (60 steps, 1% margin) contain every eigenvalue of each term
+    and are no wider than the Gershgorin intervals (narrower for the chain's H1)."""
+    if kind == "chain":
+        H1, H2 = chain(10)
+        A1, A2 = H1.to_scipy().toarray(), H2.to_scipy().toarray()
+        mk = lambda: B.DeviceHamiltonian.from_csr(H1, H2)
+    else:
+        A1 = inputs.powerlaw_hermitian(300, 1.5, seed=5)
+        A2 = inputs.powerlaw_hermitian(300, 1.5, seed=6)
+        mk = lambda: B.DeviceHamiltonian.from_dense(A1, A2)
+    c = B.Context(max_dim=A1.shape[0], max_batch=1)
+    g = B.magnus_spectral_bounds(c, mk())
+    lz = B.magnus_spectral_bounds_lanczos(c, mk(), steps=60, margin=0.01)
+    for term, A in (("H1", A1), ("H2", A2)):
+        lam = np.linalg.eigvalsh(A)
+        tg, tl = getattr(g.struct, term), getattr(lz.struct, term)
+        assert tl.lam_min <= lam[0] and lam[-1] <= tl.lam_max, (term, tl.lam_min, tl.lam_max, lam[0], lam[-1])
+        assert tl.lam_max - tl.lam_min <= tg.lam_max - tg.lam_min + 1e-12
+    if kind == "chain":
+        assert lz.struct.H1.lam_max - lz.struct.H1.lam_min < 0.8 * (g.struct.H1.lam_max - g.struct.H1.lam_min)
+    with pytest.raises(B.MagnusError):
+        B.magnus_spectral_bounds_lanczos(c, mk(), steps=1)
+    c.close()
+
+
+def test_lanczos_bounds_propagation_matches_oracle(ctx):
+    """With the Lanczos estimates the chain n = 10 run (100 Cf4 and M4 steps) and two Cf4
+    steps of the full n = 20 chain still match the oracle within the budget."""
+    cfg = inputs.CONFIGS["chain_n10"]
+    H1, H2 = chain(10)
+    ham = B.magnus_spectral_bounds_lanczos(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    f = inputs.cos_field(cfg["omega"])
+    psi0 = inputs.random_states(1024, seed=cfg["psi_seed"])
+    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), f)
+    for method in ("CF4", "M4"):
+        psi = dev(psi0)
+        B.propagate(ctx, ham, B.METHODS[method], cfg["tau"], _field_nodes(method, f, 0.0, cfg["tau"], cfg["nsteps"]),
+                    psi, opts=B.leja_opts(BUDGET, tol_mode=1))
+        ref = mg.propagate(method, P, cfg["tau"], cfg["nsteps"], psi0, expm="taylor")
+        assert rel(host(psi), ref) <= BUDGET, method
+    cfg = inputs.CONFIGS["chain_n20"]
+    H1, H2 = chain(20)
+    ham = B.magnus_spectral_bounds_lanczos(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    f = inputs.cos_field(cfg["omega"])
+    psi0 = inputs.random_states(1 << 20, seed=cfg["psi_seed"])
+    tol_e = BUDGET / (2 * cfg["nsteps"])
+    psi = dev(psi0)
+    B.propagate(ctx, ham, B.CF4, cfg["tau"], _field_nodes("CF4", f, 0.0, cfg["tau"], 2), psi, opts=B.leja_opts(tol_e))
+    ref = mg.propagate("CF4", mg.two_term(H1.to_scipy(), H2.to_scipy(), f), cfg["tau"], 2, psi0, expm="taylor")
+    assert rel(host(psi), ref) <= 50 * tol_e * 2
