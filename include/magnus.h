@@ -289,10 +289,12 @@ typedef struct {
 /* nsteps steps of `method` for several independent problems of different
  * sizes (the one-step scheme of Section 2 on each).  CSR problems of the
  * product-of-exponentials methods (Cf4, Cf4:3, M2) whose dimension is at most
- * 4096 all run in one persistent launch (one workgroup per state carries
- * every step with its vectors in LDS); the others run as batched
- * propagations.  Tolerances as in propagate (tol_mode 1: budget over the
- * exponentials of each state).  Errors as propagate. */
+ * 4096 run in persistent launches (one workgroup per state carries every
+ * step with its vectors in LDS; up to 256 or max_batch states per launch);
+ * the others run first, as batched propagations, each followed by a host
+ * wait that reports a non-finite norm (ENAN) at once.  Tolerances as in
+ * propagate (tol_mode 1: budget over the exponentials of each state).
+ * Errors as propagate. */
 int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_t nprob, int32_t method,
                             double tau, int64_t nsteps, const magnus_leja_opts* opts, magnus_stats* stats,
                             magnus_stream stream);

@@ -74,6 +74,7 @@ struct magnus_ctx {
   double2* vecs = nullptr;     // kNumVec vectors of max_dim * max_batch entries
   Slot* slots = nullptr;       // one control block per state of a batch
   int nslots = 0;
+  int sticky_status = 0;       // status bits of slots reset inside the current call
   ColParam* table = nullptr;   // kTableCap entries
   unsigned char* arena = nullptr;  // kArenaBytes
   int persist = 1;                 // MAGNUS_PERSIST=0 disables the small-state kernel
@@ -418,6 +419,7 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
 
 int begin_call(magnus_ctx* ctx, hipStream_t s) {
   HIP_TRY(hipSetDevice(ctx->device));
+  ctx->sticky_status = 0;
   HIP_TRY(magnus::launch_slot_reset(ctx->slots, ctx->nslots, s));
   return MAGNUS_OK;
 }
@@ -446,6 +448,7 @@ int end_call(magnus_ctx* ctx, const Acc& acc, double tol_e, magnus_stats* st, hi
   st->substeps = acc.substeps;
   st->planned_iters = acc.planned;
   st->iters = iters + acc.extra_iters;
+  status |= ctx->sticky_status;
   st->hv_products = st->iters * acc.products_per_iter;
   st->max_degree_used = acc.max_m;
   st->max_substeps_used = acc.max_s;
@@ -1207,6 +1210,7 @@ int magnus_check(magnus_ctx* ctx, magnus_stream stream) {
   int status = 0;
   int rc = read_slots(ctx, s, &iters, &status);
   if (rc) return rc;
+  status |= ctx->sticky_status;
   if (status & 1) return fail(MAGNUS_ENAN, "non-finite vector norm met on the device");
   return MAGNUS_OK;
 }
@@ -1609,8 +1613,9 @@ int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_
     o.tol = tol_e;
     o.tol_mode = 0;
     magnus_stats ps{};
-    rc = propagate(ctx, &P.h, method, tau, nsteps, P.f_nodes, P.batch_f, P.psi, P.batch, nullptr, 1, &o,
-                   stats ? &ps : nullptr, stream);
+    // with stats, so a non-finite norm in this problem surfaces here (the slots are reset afterwards)
+    rc = propagate(ctx, &P.h, method, tau, nsteps, P.f_nodes, P.batch_f, P.psi, P.batch, nullptr, 1, &o, &ps,
+                   stream);
     if (rc) return rc;
     acc.exponentials += ps.exponentials;
     acc.substeps += ps.substeps;
@@ -1618,11 +1623,25 @@ int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_
     acc.max_m = std::max(acc.max_m, ps.max_degree_used);
     acc.max_s = std::max(acc.max_s, ps.max_substeps_used);
     acc.max_bound = std::max(acc.max_bound, ps.max_err_bound);
-    if (stats) acc.extra_iters += ps.iters;  // counted by the nested call
+    acc.extra_iters += ps.iters;  // counted by the nested call
   }
   if (!sst.empty() && nsteps > 0) {
     if (!big.empty()) HIP_TRY(magnus::launch_slot_reset(ctx->slots, ctx->nslots, s));
-    if ((rc = persist_steps(ctx, hs, sst, S, tau, 0, nsteps, tol_e, opts, &acc, s))) return rc;
+    // one launch per group of at most nslots states (one control slot each); the
+    // slots keep counting, so groups after the first are folded into extra_iters
+    for (size_t g0 = 0; g0 < sst.size(); g0 += (size_t)ctx->nslots) {
+      const size_t g1 = std::min(sst.size(), g0 + (size_t)ctx->nslots);
+      if (g0 > 0) {
+        long long it = 0;
+        int st = 0;
+        if ((rc = read_slots(ctx, s, &it, &st))) return rc;  // the previous group's counters and status
+        acc.extra_iters += it;
+        ctx->sticky_status |= st;
+        HIP_TRY(magnus::launch_slot_reset(ctx->slots, ctx->nslots, s));
+      }
+      std::vector<SmallState> part(sst.begin() + (long)g0, sst.begin() + (long)g1);
+      if ((rc = persist_steps(ctx, hs, part, S, tau, 0, nsteps, tol_e, opts, &acc, s))) return rc;
+    }
   }
   return end_call(ctx, acc, tol_e, stats, s);
 }

@@ -618,3 +618,25 @@ def test_lanczos_bounds_propagation_matches_oracle(ctx):
     B.propagate(ctx, ham, B.CF4, cfg["tau"], _field_nodes("CF4", f, 0.0, cfg["tau"], 2), psi, opts=B.leja_opts(tol_e))
     ref = mg.propagate("CF4", mg.two_term(H1.to_scipy(), H2.to_scipy(), f), cfg["tau"], 2, psi0, expm="taylor")
     assert rel(host(psi), ref) <= 50 * tol_e * 2
+
+
+def test_ragged_more_small_states_than_control_slots():
+    """300 small states (more than the context's 256 control slots) run as two
+    persistent launches; every state matches its single-state propagation."""
+    tau, nsteps = 0.01, 5
+    c = B.Context(max_dim=256, max_batch=4)
+    H1, H2 = chain(8)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    psi0 = inputs.random_states(256, seed=601, batch=300)
+    fields = [inputs.cos_field(2.0, 1.0 + k / 300) for k in range(300)]
+    fn = np.stack([_field_nodes("CF4", f, 0.0, tau, nsteps) for f in fields])
+    psi = dev(psi0)
+    st = B.magnus_propagate_ragged(c, [(ham, psi, fn)], B.CF4, tau, opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    out = host(psi)
+    assert st["exponentials"] == 2 * nsteps * 300
+    assert st["iters"] > 0
+    P0 = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[0])
+    P1 = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[299])
+    assert rel(out[0], mg.propagate("CF4", P0, tau, nsteps, psi0[0], expm="taylor")) <= BUDGET
+    assert rel(out[299], mg.propagate("CF4", P1, tau, nsteps, psi0[299], expm="taylor")) <= BUDGET
+    c.close()
