@@ -138,7 +138,8 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = ev0.elapsed_time(ev1)
-        kinds = {"leja": B.KERNEL_CSR_LEJA, "split": B.KERNEL_CSR_SPLIT, "comm": B.KERNEL_CSR_COMM}
+        kinds = {"leja": B.KERNEL_CSR_LEJA, "split": B.KERNEL_CSR_SPLIT, "comm": B.KERNEL_CSR_COMM,
+                 "leja3": B.KERNEL_CSR_LEJA3}
         kt = {k: ctx.timing_read(v) for k, v in kinds.items()}
         ctx.timing(False)
         ctx.check()
@@ -172,6 +173,18 @@ def main():
             "split_kernel_avg_us": 1e3 * kt4["split"][0] / max(kt4["split"][1], 1),
             "comm_kernel_avg_us": 1e3 * kt4["comm"][0] / max(kt4["comm"][1], 1),
             "tol_per_exp": tol_m4,
+        }
+        # M4 again with K = i[H1, H2] assembled on the device: one three-term pass per iteration
+        kms, _ = _timed(lambda: B.magnus_csr_commutator(ctx, ham))
+        ms5, wall5, st5, kt5 = run("M4", tol_m4)
+        print(f"[bench] M4 (assembled commutator) {K} steps: {ms5:.1f} ms, iters {st5['iters']}", file=sys.stderr,
+              flush=True)
+        out["m4_assembled_commutator"] = {
+            "steps_per_s": K / (ms5 * 1e-3),
+            "ms_per_step": ms5 / K,
+            "leja_iters_per_step": st5["iters"] / K,
+            "commutator_assembly_ms": kms,
+            "leja3_kernel_avg_us": 1e3 * kt5["leja3"][0] / max(kt5["leja3"][1], 1),
         }
 
     cpu = None

@@ -174,6 +174,19 @@ int magnus_reserve_dense(magnus_ctx* ctx, int64_t dim);
  * max_dim), EHIP. */
 int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
 
+/* Assemble the commutator K = i [H1, H2] of two CSR terms in the context
+ * (Section 2, Method M4; Section 4 forms the M4 commutator explicitly) and set
+ * h->k_min, h->k_max from K's Gershgorin discs.  Every row of H1 H2 - H2 H1 is
+ * formed on the device from its products (one wave per row: at most 1024
+ * products per row, else ENOMEM), equal columns summed in a fixed order,
+ * exact zeros dropped.  Afterwards M4 steps and commutator exponents on these
+ * terms run one pass over H1, H2 and K per Leja iteration instead of the two
+ * matrix-free passes.  The context keeps K (allocating its arrays) for this
+ * pair of terms, recognised by their row_ptr and val pointers and dim; a
+ * later call for another pair replaces it.  Synchronous.
+ * Errors: EINVAL (null or non-CSR terms, malformed CSR), EDOMAIN, ENOMEM, EHIP. */
+int magnus_csr_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
+
 /* Prepare Method M6 (Section 2) on two dense terms.  For H(t) = H1 + f(t) H2
  * the nested commutators of the M6 exponent expand into a linear combination,
  * with scalars that depend on the step's three field samples, of ten fixed
@@ -360,6 +373,7 @@ int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch,
 #define MAGNUS_KERNEL_CSR_MULTI  4  /* two-term CSR Leja iteration on a group of states */
 #define MAGNUS_KERNEL_DENSE_MFMA 5  /* dense group Leja iteration (FP64 MFMA GEMM) */
 #define MAGNUS_KERNEL_PERSIST    6  /* whole small-state propagations, one workgroup per state */
+#define MAGNUS_KERNEL_CSR_LEJA3  7  /* three-term CSR Leja iteration (assembled commutator) */
 
 /* enable = 1: from now on bracket every iteration kernel the context launches
  * with a pair of HIP events on the call's stream (previous records are

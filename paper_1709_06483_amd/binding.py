@@ -67,8 +67,8 @@ EXPORTS = ("magnus_create", "magnus_destroy", "magnus_last_error", "magnus_check
            "magnus_timing", "magnus_timing_read", "magnus_reserve_dense", "magnus_adjoint_workspace_bytes",
            "magnus_propagate_adjoint", "magnus_propagate_ragged", "magnus_method_nodes",
            "magnus_dense_commutator", "magnus_dense_m6_prepare", "magnus_autotune",
-           "magnus_spectral_bounds_lanczos")
-KERNEL_PERSIST = 6
+           "magnus_spectral_bounds_lanczos", "magnus_csr_commutator")
+KERNEL_PERSIST, KERNEL_CSR_LEJA3 = 6, 7
 KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA, KERNEL_CSR_MULTI, KERNEL_DENSE_MFMA = 0, 1, 2, 3, 4, 5
 
 
@@ -106,6 +106,7 @@ def lib():
         "magnus_dense_m6_prepare": (C.c_int, [vp, P(Hamiltonian), vp]),
         "magnus_autotune": (C.c_int, [vp, P(Hamiltonian), i32, P(i32), P(i32), P(dbl), P(dbl), vp]),
         "magnus_spectral_bounds_lanczos": (C.c_int, [vp, P(Hamiltonian), i32, dbl, vp]),
+        "magnus_csr_commutator": (C.c_int, [vp, P(Hamiltonian), vp]),
         "magnus_adjoint_workspace_bytes": (i64, [i64, i64, i32]),
         "magnus_propagate_ragged": (C.c_int, [vp, P(Problem), i32, i32, dbl, i64, P(LejaOpts), P(Stats), vp]),
         "magnus_propagate_adjoint": (C.c_int, [vp, P(Hamiltonian), dbl, i64, P(dbl), P(dbl), i32, vp, vp, i32, vp,
@@ -275,6 +276,12 @@ def magnus_spectral_bounds_lanczos(ctx: Context, ham: DeviceHamiltonian, steps: 
                                    margin: float = 0.01) -> DeviceHamiltonian:
     """Lanczos estimates of the terms' spectra (tighter than Gershgorin, not rigorous)."""
     _check(lib().magnus_spectral_bounds_lanczos(ctx.handle, C.byref(ham.struct), steps, margin, _stream()))
+    return ham
+
+
+def magnus_csr_commutator(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:
+    """Assemble K = i[H1, H2] of CSR terms in the context (M4 then runs one pass per iteration)."""
+    _check(lib().magnus_csr_commutator(ctx.handle, C.byref(ham.struct), _stream()))
     return ham
 
 

@@ -85,6 +85,13 @@ struct magnus_ctx {
   const void* comm_h1 = nullptr;  // the dense pair K belongs to (value pointers, dim, ld)
   const void* comm_h2 = nullptr;
   int64_t comm_n = 0, comm_ld = 0;
+  // magnus_csr_commutator: K = i[H1, H2] as CSR (row stride-free arrays of
+  // kc_rows + 1, kc_cap entries) for the pair of CSR terms recognised by kc_key
+  int* kc_rp = nullptr;
+  int* kc_ci = nullptr;
+  double2* kc_val = nullptr;
+  int64_t kc_rows = 0, kc_cap = 0, kc_nnz = 0;
+  std::tuple<const void*, const void*, const void*, const void*, int64_t> kc_key{nullptr, nullptr, nullptr, nullptr, 0};
   // magnus_dense_m6_prepare: the nested commutators of M6, kM6Mats matrices of
   // m6_dim^2 entries, with Gershgorin enclosures, for the pair K belongs to
   double2* m6 = nullptr;
@@ -245,6 +252,13 @@ struct ExpOp {
   double lo = 0.0, hi = 0.0;
 };
 
+// Whether the context holds K = i[H1, H2] of this pair of CSR terms.
+bool csr_comm_ready(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  return ctx->kc_rp && h->H1.format == MAGNUS_CSR &&
+         ctx->kc_key == std::make_tuple((const void*)h->H1.row_ptr, h->H1.val, (const void*)h->H2.row_ptr, h->H2.val,
+                                        h->H1.dim);
+}
+
 // Whether the context holds K = i[H1, H2] of this pair of dense terms.
 bool dense_comm_ready(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
   return ctx->comm && ctx->comm_h1 == h->H1.val && ctx->comm_h2 == h->H2.val && ctx->comm_n == h->H1.dim &&
@@ -338,6 +352,16 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA, s,
                   [&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }));
     HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
+    return MAGNUS_OK;
+  }
+  if (csr_comm_ready(ctx, h)) {
+    // assembled commutator: one pass over H1, H2 and K
+    CsrDev t3{ctx->kc_rp, ctx->kc_ci, ctx->kc_val};
+    a.x1 = win;
+    a.x2 = win;
+    HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA3, s,
+                  [&] { return magnus::launch_csr3_iter(t1, t2, t3, dim, a, P.scale * op.kappa, s); }));
+    HIP_TRY(magnus::launch_leja_decide(a, magnus::csr3_grid(dim), s));
     return MAGNUS_OK;
   }
   // commutator: pass 1 writes U = H1 w, V = H2 w; pass 2 applies H1 V and H2 U
@@ -1035,6 +1059,71 @@ int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_strea
   return MAGNUS_OK;
 }
 
+int magnus_csr_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream) {
+  if (!ctx || !h) return fail(MAGNUS_EINVAL, "null argument");
+  int rc = check_ham(ctx, h, 0);
+  if (rc) return rc;
+  if (h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "magnus_csr_commutator needs CSR terms");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if ((rc = ensure_valid(ctx, h, s))) return rc;
+  const int64_t dim = h->H1.dim;
+  CsrDev A{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
+  CsrDev Bm{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
+  ctx->kc_key = std::make_tuple(nullptr, nullptr, nullptr, nullptr, (int64_t)0);
+  // count pass: per-row sizes in a work vector, the overflow flag in the scan buffer
+  int* counts = reinterpret_cast<int*>(ctx->vec(kV));
+  int* overflow = reinterpret_cast<int*>(ctx->scan);
+  HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), s));
+  HIP_TRY(magnus::launch_csr_commutator(false, A, Bm, (int)dim, counts, nullptr, nullptr, nullptr, overflow, s));
+  std::vector<int> cnt((size_t)dim);
+  int ovf = 0;
+  HIP_TRY(hipMemcpyAsync(cnt.data(), counts, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ovf)
+    return fail(MAGNUS_ENOMEM, "a row of H1 H2 - H2 H1 lists more than %d products (use the matrix-free commutator)",
+                magnus::kCommCap);
+  std::vector<int> rp((size_t)dim + 1, 0);
+  for (int64_t r = 0; r < dim; ++r) {
+    if ((int64_t)rp[r] + cnt[r] > INT32_MAX) return fail(MAGNUS_ENOMEM, "the commutator has more than 2^31 entries");
+    rp[r + 1] = rp[r] + cnt[r];
+  }
+  const int64_t nnz = rp[dim];
+  if (ctx->kc_rows < dim || ctx->kc_cap < std::max<int64_t>(nnz, 1)) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ctx->kc_rp) HIP_TRY(hipFree(ctx->kc_rp));
+    if (ctx->kc_ci) HIP_TRY(hipFree(ctx->kc_ci));
+    if (ctx->kc_val) HIP_TRY(hipFree(ctx->kc_val));
+    ctx->kc_rp = nullptr;
+    ctx->kc_ci = nullptr;
+    ctx->kc_val = nullptr;
+    ctx->kc_rows = ctx->kc_cap = 0;
+    HIP_TRY(hipMalloc(&ctx->kc_rp, sizeof(int) * (size_t)(dim + 1)));
+    HIP_TRY(hipMalloc(&ctx->kc_ci, sizeof(int) * (size_t)std::max<int64_t>(nnz, 1)));
+    HIP_TRY(hipMalloc(&ctx->kc_val, sizeof(double2) * (size_t)std::max<int64_t>(nnz, 1)));
+    ctx->kc_rows = dim;
+    ctx->kc_cap = std::max<int64_t>(nnz, 1);
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->kc_rp, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(magnus::launch_csr_commutator(true, A, Bm, (int)dim, counts, ctx->kc_rp, ctx->kc_ci, ctx->kc_val, overflow,
+                                        s));
+  ctx->kc_nnz = nnz;
+  magnus_term kt{};
+  kt.format = MAGNUS_CSR;
+  kt.dim = dim;
+  kt.nnz = nnz;
+  kt.row_ptr = ctx->kc_rp;
+  kt.col_idx = ctx->kc_ci;
+  kt.val = ctx->kc_val;
+  double lo, hi;
+  if ((rc = csr_scan(ctx, kt, s, &lo, &hi))) return rc;
+  h->k_min = lo;
+  h->k_max = hi;
+  ctx->kc_key = std::make_tuple((const void*)h->H1.row_ptr, h->H1.val, (const void*)h->H2.row_ptr, h->H2.val, dim);
+  return MAGNUS_OK;
+}
+
 int magnus_dense_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream) {
   int rc = magnus_dense_commutator(ctx, h, stream);
   if (rc) return rc;
@@ -1195,6 +1284,9 @@ int magnus_destroy(magnus_ctx* ctx) {
   if (ctx->assembled) (void)hipFree(ctx->assembled);
   if (ctx->comm) (void)hipFree(ctx->comm);
   if (ctx->m6) (void)hipFree(ctx->m6);
+  if (ctx->kc_rp) (void)hipFree(ctx->kc_rp);
+  if (ctx->kc_ci) (void)hipFree(ctx->kc_ci);
+  if (ctx->kc_val) (void)hipFree(ctx->kc_val);
   if (ctx->partials) (void)hipFree(ctx->partials);
   if (ctx->scan) (void)hipFree(ctx->scan);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -1548,7 +1640,7 @@ int magnus_timing(magnus_ctx* ctx, int32_t enable) {
 
 int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches) {
   if (!ctx || !total_ms || !launches) return fail(MAGNUS_EINVAL, "null argument");
-  if (kind < MAGNUS_KERNEL_CSR_LEJA || kind > MAGNUS_KERNEL_PERSIST) return fail(MAGNUS_EINVAL, "kernel class %d", kind);
+  if (kind < MAGNUS_KERNEL_CSR_LEJA || kind > MAGNUS_KERNEL_CSR_LEJA3) return fail(MAGNUS_EINVAL, "kernel class %d", kind);
   HIP_TRY(hipSetDevice(ctx->device));
   double t = 0.0;
   int64_t n = 0;

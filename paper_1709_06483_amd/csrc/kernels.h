@@ -181,6 +181,19 @@ hipError_t launch_scale(const double2* x, double sc, double2* y, long long n, hi
 // dst (interleaved pair) = [0; v].
 hipError_t launch_frechet_init(const double2* v, double2* dst, int dim, hipStream_t s);
 
+// ---- assembled CSR commutator (Method M4 on CSR terms) ----
+// Products of one row of H1 H2 and H2 H1 that the assembly kernel holds.
+constexpr int kCommCap = 1024;
+// K = i (A B - B A), one wave per row.  Count pass (fill = false): counts[r] =
+// entries of row r, *overflow = 1 if a row lists more than kCommCap products.
+// Fill pass: column indices and values at rp_out[r].
+hipError_t launch_csr_commutator(bool fill, const CsrDev& A, const CsrDev& Bm, int dim, int* counts,
+                                 const int* rp_out, int* ci_out, double2* val_out, int* overflow, hipStream_t s);
+// One Leja iteration on a1 H1 + a2 H2 + a3 K (kLeja semantics, x = a.x1).
+int csr3_grid(int dim);
+hipError_t launch_csr3_iter(const CsrDev& t1, const CsrDev& t2, const CsrDev& t3, int dim, const IterArgs& a,
+                            double a3, hipStream_t s);
+
 // ---- whole propagations in one workgroup per state (small dimensions) ----
 
 struct PersistProblem {
