@@ -284,6 +284,11 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
  *               slot j receives psi after j*every_k steps (slot 0 = psi0), and
  *               the last slot psi after nsteps steps.
  *   every_k     checkpoint spacing (>= 1; ignored when checkpoints is NULL).
+ * CSR states of the product-of-exponentials methods run the whole call in one
+ * persistent launch (one workgroup per state, vectors in LDS) when the
+ * dimension is at most 1024, 2048 with 4 or more states, 4096 with 32 or more
+ * (environment MAGNUS_PERSIST, read at magnus_create: 0 never, 2 always up to
+ * 4096); larger ones launch each Leja iteration over the grid.
  * Errors as expmv_leja. */
 int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, double tau,
               int64_t nsteps, const double* f_nodes, int32_t batch_f, void* psi, int32_t batch,
@@ -301,9 +306,11 @@ typedef struct {
 
 /* nsteps steps of `method` for several independent problems of different
  * sizes (the one-step scheme of Section 2 on each).  CSR problems of the
- * product-of-exponentials methods (Cf4, Cf4:3, M2) whose dimension is at most
- * 4096 run in persistent launches (one workgroup per state carries every
- * step with its vectors in LDS; up to 256 or max_batch states per launch);
+ * product-of-exponentials methods (Cf4, Cf4:3, M2) run in persistent launches
+ * (one workgroup per state carries every step with its vectors in LDS; up to
+ * 256 or max_batch states per launch) when their dimension is within the
+ * cap stated at propagate, for a state count taken over all CSR problems of
+ * dimension at most 4096 in the call;
  * the others run first, as batched propagations, each followed by a host
  * wait that reports a non-finite norm (ENAN) at once.  Tolerances as in
  * propagate (tol_mode 1: budget over the exponentials of each state).

@@ -77,7 +77,7 @@ struct magnus_ctx {
   int sticky_status = 0;       // status bits of slots reset inside the current call
   ColParam* table = nullptr;   // kTableCap entries
   unsigned char* arena = nullptr;  // kArenaBytes
-  int persist = 1;                 // MAGNUS_PERSIST=0 disables the small-state kernel
+  int persist = 1;  // MAGNUS_PERSIST: 0 never, 1 by size and state count, 2 every state of at most kSmallDim
   double2* assembled = nullptr;  // magnus_reserve_dense
   int64_t assembled_dim = 0;
   double2* comm = nullptr;       // magnus_dense_commutator: K = i[H1, H2], row stride comm_dim
@@ -832,8 +832,23 @@ struct SmallState {
   const double* fn;  // this state's field samples, [nsteps][q]
 };
 
-bool small_ok(magnus_ctx* ctx, const magnus_hamiltonian* h) {
-  return ctx->persist && h->H1.format == MAGNUS_CSR && h->H1.dim <= kSmallDim;
+// One workgroup's iteration time grows with the dimension, while the
+// per-iteration grid launches of the other paths cost about the same for any
+// dimension up to a few thousand rows; the persistent launch pays off when its
+// states are small or many.  Measured crossover (MI355X, Cf4 on spin chains,
+// state-steps/s persistent vs grid): 1024 rows win from one state on; 2048
+// rows lose at one state (5.1k vs 7.5k) and win at four (19k vs 14k); 4096
+// rows lose up to 16 states (38k vs 40k) and win at 64 (151k vs 59k).
+int64_t small_cap(const magnus_ctx* ctx, int64_t nstates) {
+  if (ctx->persist == 0) return 0;
+  if (ctx->persist >= 2 || nstates >= 32) return kSmallDim;
+  return nstates >= 4 ? 2048 : 1024;
+}
+
+bool small_candidate(const magnus_hamiltonian* h) { return h->H1.format == MAGNUS_CSR && h->H1.dim <= kSmallDim; }
+
+bool small_ok(magnus_ctx* ctx, const magnus_hamiltonian* h, int64_t nstates) {
+  return small_candidate(h) && h->H1.dim <= small_cap(ctx, nstates);
 }
 
 // Steps n0..n1-1 of every state in one launch.
@@ -1578,7 +1593,7 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
     return f_nodes[((batch_f == 1 ? 0 : (int64_t)c) * nsteps + n) * S.q + j];
   };
   const bool grouped = !S.commutator && multi_ok(h, 0.0) && batch > 1;
-  const bool small = !S.commutator && small_ok(ctx, h);
+  const bool small = !S.commutator && small_ok(ctx, h, batch);
   std::vector<SmallState> sst;
   if (small)
     for (int32_t c = 0; c < batch; ++c)
@@ -1684,9 +1699,12 @@ int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_
   std::vector<const magnus_hamiltonian*> hs;
   std::vector<SmallState> sst;
   std::vector<int> big;
+  int64_t ncand = 0;  // states that could share the persistent launches
+  for (int32_t i = 0; i < nprob; ++i)
+    if (!S.commutator && small_candidate(&probs[i].h)) ncand += probs[i].batch;
   for (int32_t i = 0; i < nprob; ++i) {
     const magnus_problem& P = probs[i];
-    if (!S.commutator && small_ok(ctx, &P.h)) {
+    if (!S.commutator && small_ok(ctx, &P.h, ncand)) {
       const int pi = (int)hs.size();
       hs.push_back(&P.h);
       double2* psi = reinterpret_cast<double2*>(P.psi);

@@ -441,9 +441,13 @@ def test_small_state_propagation_paths_agree(persist, monkeypatch):
     c.close()
 
 
-def test_ragged_batch_matches_oracle():
-    """Chains of 8, 10, 12 and 15 spins with several states each, one call; the
-    three small problems share one persistent launch, the n = 15 chain runs batched."""
+@pytest.mark.parametrize("persist", ["1", "2"])
+def test_ragged_batch_matches_oracle(persist, monkeypatch):
+    """Chains of 8, 10, 12 and 15 spins with several states each, one call.  With
+    the size rule (persist 1, nine small states: cap 2048) the 8- and 10-spin
+    problems share one persistent launch and the 12- and 15-spin chains run
+    batched; with persist 2 the 12-spin chain joins the persistent launch."""
+    monkeypatch.setenv("MAGNUS_PERSIST", persist)
     tau, nsteps = 0.01, 12
     c = B.Context(max_dim=1 << 15, max_batch=4)
     probs, refs = [], []
@@ -639,4 +643,31 @@ def test_ragged_more_small_states_than_control_slots():
     P1 = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[299])
     assert rel(out[0], mg.propagate("CF4", P0, tau, nsteps, psi0[0], expm="taylor")) <= BUDGET
     assert rel(out[299], mg.propagate("CF4", P1, tau, nsteps, psi0[299], expm="taylor")) <= BUDGET
+    c.close()
+
+
+@pytest.mark.parametrize("n,batch,persistent", [(10, 1, True), (11, 1, False), (11, 4, True),
+                                                (12, 16, False), (12, 32, True)])
+def test_small_state_path_selection(n, batch, persistent, monkeypatch):
+    """The persistent kernel takes a call when the dimension is within the cap for
+    its state count (1024; 2048 from 4 states; 4096 from 32), otherwise every
+    Leja iteration is a grid launch; both results match the oracle."""
+    monkeypatch.setenv("MAGNUS_PERSIST", "1")
+    tau, nsteps = 0.01, 3
+    H1, H2 = chain(n)
+    c = B.Context(max_dim=1 << n, max_batch=batch)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    psi0 = inputs.random_states(1 << n, seed=700 + n, batch=batch)
+    f = inputs.cos_field(2.0)
+    psi = dev(psi0)
+    c.timing(True)
+    B.propagate(c, ham, B.CF4, tau, _field_nodes("CF4", f, 0.0, tau, nsteps), psi,
+                opts=B.leja_opts(BUDGET, tol_mode=1))
+    launches = c.timing_read(B.KERNEL_PERSIST)[1]
+    c.timing(False)
+    assert (launches > 0) == persistent
+    out = host(psi)
+    ref = mg.propagate("CF4", mg.two_term(H1.to_scipy(), H2.to_scipy(), f), tau, nsteps, psi0[batch - 1],
+                       expm="taylor")
+    assert rel(out[batch - 1], ref) <= BUDGET
     c.close()
