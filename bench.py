@@ -239,7 +239,8 @@ def main():
 
 CSR_KERNEL_NAMES = {0: "csr2_wave_kernel<8, kLeja>", 1: "csr2_iter_kernel<64, kLeja>", 2: "csr2_rowlane_kernel<64, kLeja>",
                     3: "csr2_rowlane_kernel<32, kLeja>", 4: "csr2_rowlane_kernel<128, kLeja>",
-                    5: "csr2_wave_kernel<8, kLeja>", 6: "csr2_wave_kernel<16, kLeja>"}
+                    5: "csr2_wave_kernel<8, kLeja>", 6: "csr2_wave_kernel<16, kLeja>",
+                    7: "csr2_stream_kernel"}
 
 
 def kernel_source_digest(sources=None) -> str:

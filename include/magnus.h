@@ -356,15 +356,16 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
 /* Autotuner for the H·v stream that Section 3 reduces the method's cost to:
  * times, on the device, each row mapping of the single-state CSR Leja
  * iteration on these terms (variant codes 1 nonzero streaming, 2-4 a row per
- * lane in blocks of 64/32/128 rows, 5-6 wave tiles of 8/16 rows; 5 timed
- * launches each) and, when batch > 1, the multi-state iteration with 2, 4, 8,
+ * lane in blocks of 64/32/128 rows, 5-6 wave tiles of 8/16 rows, 7 runs of 8
+ * wave tiles of 8 rows streamed through LDS one tile ahead;
+ * 5 timed launches each) and, when batch > 1, the multi-state iteration with 2, 4, 8,
  * 16 and 32 states per pass (up to batch; cost per state), and keeps the
  * fastest for these terms (recognised by H1's row_ptr and dim) in the
  * context: later calls use them.  Results differ from untuned calls only in
  * rounding (another summation order); the MAGNUS_CSR_VARIANT environment
  * variable, when set, still wins.  Overwrites the context's work vectors.
  *   variant, group       HOST out (may be NULL): the chosen code and group size
- *   variant_us[6], group_us[5]  HOST out (may be NULL): measured microseconds per
+ *   variant_us[7], group_us[5]  HOST out (may be NULL): measured microseconds per
  *                        launch (group entries NAN where not tried).
  * CSR terms only.  Synchronous.  Errors: EINVAL, ENOMEM, EHIP. */
 int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch, int32_t* variant,

@@ -292,19 +292,20 @@ def magnus_dense_commutator(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamil
 
 
 CSR_VARIANTS = {1: "nonzero streaming", 2: "row per lane, 64 rows", 3: "row per lane, 32 rows",
-                4: "row per lane, 128 rows", 5: "wave tiles of 8 rows", 6: "wave tiles of 16 rows"}
+                4: "row per lane, 128 rows", 5: "wave tiles of 8 rows", 6: "wave tiles of 16 rows",
+                7: "streamed wave tiles"}
 
 
 def magnus_autotune(ctx: Context, ham: DeviceHamiltonian, batch: int = 1) -> dict:
     """Time the CSR kernel variants (and multi-state group sizes when batch > 1) on these
     terms and keep the fastest in the context.  Returns the choices and the timings."""
     v, g = C.c_int32(), C.c_int32()
-    vus = np.zeros(6)
+    vus = np.zeros(len(CSR_VARIANTS))
     gus = np.zeros(5)
     _check(lib().magnus_autotune(ctx.handle, C.byref(ham.struct), batch, C.byref(v), C.byref(g), _dptr(vus),
                                  _dptr(gus), _stream()))
     return {"variant": int(v.value), "variant_name": CSR_VARIANTS[int(v.value)], "group": int(g.value),
-            "variant_us": {CSR_VARIANTS[k + 1]: float(vus[k]) for k in range(6)},
+            "variant_us": {CSR_VARIANTS[k + 1]: float(vus[k]) for k in range(len(CSR_VARIANTS))},
             "group_us": {str(b): (None if np.isnan(gus[i]) else float(gus[i])) for i, b in enumerate((2, 4, 8, 16, 32))}}
 
 

@@ -42,6 +42,7 @@ def build(verbose: bool = False) -> str:
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels_persist.hip"), "-o", os.path.join(OBJ, "kernels_persist.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels_gemm.hip"), "-o", os.path.join(OBJ, "kernels_gemm.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels_comm.hip"), "-o", os.path.join(OBJ, "kernels_comm.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels_stream.hip"), "-o", os.path.join(OBJ, "kernels_stream.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "abi.hip"), "-o", os.path.join(OBJ, "abi.o")],
     ]
     with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
@@ -55,7 +56,8 @@ def build(verbose: bool = False) -> str:
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC",
            os.path.join(OBJ, "planner.o"), os.path.join(OBJ, "kernels.o"), os.path.join(OBJ, "kernels_multi.o"),
            os.path.join(OBJ, "kernels_mfma.o"), os.path.join(OBJ, "kernels_persist.o"),
-           os.path.join(OBJ, "kernels_gemm.o"), os.path.join(OBJ, "kernels_comm.o"), os.path.join(OBJ, "abi.o"),
+           os.path.join(OBJ, "kernels_gemm.o"), os.path.join(OBJ, "kernels_comm.o"),
+           os.path.join(OBJ, "kernels_stream.o"), os.path.join(OBJ, "abi.o"),
            "-o", tmp]
     _, rc, out = _run(cmd)
     if verbose or rc != 0:

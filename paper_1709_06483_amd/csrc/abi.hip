@@ -63,7 +63,7 @@ constexpr size_t kArenaBytes = 8u << 20;
 // States of at most this many entries run whole propagations in one workgroup.
 constexpr int64_t kSmallDim = magnus::kPersistMaxDim;
 // Row mappings magnus_autotune times (variant codes 1..kTuneVariants).
-constexpr int kTuneVariants = 6;
+constexpr int kTuneVariants = 7;
 
 }  // namespace
 
@@ -275,6 +275,7 @@ int variant_rows(int code, int64_t dim) {
     case 4: return -128;
     case 5: return magnus::kWaveTile + 8;
     case 6: return magnus::kWaveTile + 16;
+    case 7: return magnus::kStreamTile;
     default: return dim >= 65536 ? magnus::kWaveTile + 8 : 16;
   }
 }
@@ -284,6 +285,10 @@ int rows_per_block(magnus_ctx* ctx, const magnus_hamiltonian* h) {
   auto it = ctx->tuned_variant.find({(const void*)h->H1.row_ptr, h->H1.dim});
   return variant_rows(it == ctx->tuned_variant.end() ? 0 : it->second, h->H1.dim);
 }
+
+// The two passes of the matrix-free commutator have no streaming variant:
+// they run the 8-row wave tiles when the plain iteration streams.
+int comm_rows(int rpb) { return rpb == magnus::kStreamTile ? magnus::kWaveTile + 8 : rpb; }
 
 hipEvent_t next_event(magnus_ctx* ctx) {
   if (ctx->pool_used == ctx->pool.size()) {
@@ -365,6 +370,7 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
     return MAGNUS_OK;
   }
   // commutator: pass 1 writes U = H1 w, V = H2 w; pass 2 applies H1 V and H2 U
+  const int crpb = comm_rows(rpb);
   double2* U = ctx->vec(kU);
   double2* V = ctx->vec(kV);
   IterArgs p1 = a;
@@ -373,12 +379,12 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
   p1.wout = U;
   p1.pacc = V;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_SPLIT, s,
-                [&] { return magnus::launch_csr2_iter(magnus::kSplit, t1, t2, dim, p1, rpb, s); }));
+                [&] { return magnus::launch_csr2_iter(magnus::kSplit, t1, t2, dim, p1, crpb, s); }));
   a.x1 = V;
   a.x2 = U;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_COMM, s,
-                [&] { return magnus::launch_csr2_iter(magnus::kLejaComm, t1, t2, dim, a, rpb, s); }));
-  HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
+                [&] { return magnus::launch_csr2_iter(magnus::kLejaComm, t1, t2, dim, a, crpb, s); }));
+  HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, crpb), s));
   return MAGNUS_OK;
 }
 

@@ -63,6 +63,10 @@ constexpr int kRowLane = -64;
 // kWaveTile + R selects the wave-tile kernel with R rows per wave (R = 8, 16;
 // four waves per workgroup).
 constexpr int kWaveTile = 1000;
+// kStreamTile selects the streaming wave-tile kernel (mode kLeja only): every
+// wave walks 8 tiles of 8 rows, copying each tile's entries into LDS one tile
+// ahead.
+constexpr int kStreamTile = 2000;
 
 // Launch one iteration over `dim` rows of the two CSR terms.
 hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int dim,
@@ -70,6 +74,10 @@ hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int di
 
 // Grid size (workgroups) of launch_csr2_iter for `dim` rows.
 int csr2_grid(int dim, int rows_per_block);
+
+// The streaming kernel (kernels_stream.hip).
+hipError_t launch_csr2_stream(const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a, hipStream_t s);
+int csr2_stream_grid(int dim);
 
 // Gershgorin enclosure and structural check of one CSR term.  Writes per
 // workgroup min, max and a "malformed" flag into out[3 * grid].

@@ -719,6 +719,7 @@ __global__ void slot_reset_kernel(Slot* s, int n) {
 }  // namespace
 
 int csr2_grid(int dim, int rows_per_block) {
+  if (rows_per_block == kStreamTile) return csr2_stream_grid(dim);
   int rows = rows_per_block < 0 ? -rows_per_block : rows_per_block;
   if (rows_per_block > kWaveTile) rows = (rows_per_block - kWaveTile) * (kThreads / 64);
   return (dim + rows - 1) / rows;
@@ -726,6 +727,10 @@ int csr2_grid(int dim, int rows_per_block) {
 
 hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a,
                             int rows_per_block, hipStream_t s) {
+  if (rows_per_block == kStreamTile) {
+    if (mode != kLeja) return hipErrorInvalidValue;
+    return launch_csr2_stream(t1, t2, dim, a, s);
+  }
   const int grid = csr2_grid(dim, rows_per_block);
 #define MAGNUS_CSR_CASE(R, M) \
   if (rows_per_block == R && mode == M) { csr2_iter_kernel<R, M><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); return hipGetLastError(); }

@@ -1,0 +1,322 @@
+// Two-term CSR Leja iteration (Section 3's recurrence on a1 H1 + a2 H2), the
+// streaming wave-tile variant.
+//
+// Every wave walks `tpw` tiles of 8 consecutive rows.  A tile's column indices
+// and values (term 1's entries of its rows, then term 2's) travel from HBM
+// straight into a wave-private LDS buffer with global_load_lds (no VGPRs held
+// while in flight).  Each chunk of 256 entries is copied one step ahead: the
+// copy of the next chunk, the tile's own-row operands, the row pointers two
+// tiles ahead and the previous tile's results are all issued before the
+// gathers of the current chunk, so the wave waits once per chunk for all of
+// them together instead of once per dependent step (row pointers, then the
+// entries, then the gathers).  Lanes are laid out row-fastest (lane = g * 8 +
+// r) and each row's 8 groups are summed with shuffles in a fixed order, the
+// same order and chunking as the 8-row wave-tile kernel.
+//
+// The LDS reads of staged entries are inline ds_read instructions followed by
+// their own lgkmcnt wait: the compiler would otherwise make every LDS read wait
+// for all outstanding copies into LDS (it cannot tell the two buffers apart),
+// which would serialise the copy of the next chunk with the current one.  The
+// explicit vmcnt(0) at the top of each chunk is what orders the copy of a
+// chunk before its reads.
+#include <algorithm>
+#include <cstdint>
+
+#include "device_common.h"
+
+namespace magnus {
+namespace {
+
+using namespace dev;
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+constexpr int kSW = kThreads / 64;  // waves per workgroup
+constexpr int kSR = 8;              // rows per tile
+constexpr int kSG = 64 / kSR;       // lanes per row
+constexpr int kSCap = 256;          // entries per LDS buffer
+constexpr int kSU = kSCap / 64;     // copy instructions per buffer and array
+constexpr int kNB = 3;              // entries per lane and term in one gather round
+constexpr int kTPW = kSG;           // tiles per wave: one per lane slot g
+constexpr unsigned kNonTemporal = 2;  // cache policy of the matrix stream (nt)
+
+// Wave-private double buffers: 2 x (256 values + 256 column indices) per wave,
+// 40 KiB per workgroup, so four workgroups (16 waves) share a CU's LDS.
+struct StreamLds {
+  d2 val[kSW][2][kSCap];
+  int col[kSW][2][kSCap];
+};
+
+__device__ __forceinline__ unsigned lds_offset(const void* p) {
+  return (unsigned)(uintptr_t)(const lds_void*)p;
+}
+
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// LDS reads of staged entries: the column indices of three entries of each
+// term, and (separately, once the gathers are in flight) their values.  Each
+// statement waits for its own reads, so no instruction sees the registers
+// before the data has arrived.
+__device__ __forceinline__ void lds_read_cols(const unsigned (&ca1)[kNB], const unsigned (&ca2)[kNB],
+                                              int (&c1)[kNB], int (&c2)[kNB]) {
+  asm volatile(
+      "ds_read_b32 %0, %6\n\t"
+      "ds_read_b32 %1, %7\n\t"
+      "ds_read_b32 %2, %8\n\t"
+      "ds_read_b32 %3, %9\n\t"
+      "ds_read_b32 %4, %10\n\t"
+      "ds_read_b32 %5, %11\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(c1[0]), "=&v"(c1[1]), "=&v"(c1[2]), "=&v"(c2[0]), "=&v"(c2[1]), "=&v"(c2[2])
+      : "v"(ca1[0]), "v"(ca1[1]), "v"(ca1[2]), "v"(ca2[0]), "v"(ca2[1]), "v"(ca2[2]));
+}
+
+__device__ __forceinline__ void lds_read_vals(const unsigned (&va1)[kNB], const unsigned (&va2)[kNB],
+                                              d2 (&h1)[kNB], d2 (&h2)[kNB]) {
+  asm volatile(
+      "ds_read_b128 %0, %6\n\t"
+      "ds_read_b128 %1, %7\n\t"
+      "ds_read_b128 %2, %8\n\t"
+      "ds_read_b128 %3, %9\n\t"
+      "ds_read_b128 %4, %10\n\t"
+      "ds_read_b128 %5, %11\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(h1[0]), "=&v"(h1[1]), "=&v"(h1[2]), "=&v"(h2[0]), "=&v"(h2[1]), "=&v"(h2[2])
+      : "v"(va1[0]), "v"(va1[1]), "v"(va1[2]), "v"(va2[0]), "v"(va2[1]), "v"(va2[2]));
+}
+
+struct Tile {
+  int nr;     // rows of the tile inside the matrix (0: past the end)
+  int base1;  // first entry of term 1
+  int n1;     // entries of term 1
+  int base2;  // first entry of term 2
+  int total;  // entries of both terms
+};
+
+// Workgroup L owns 32 consecutive tiles; its wave w takes tiles L * 32 + w + 4 j,
+// j < 8 (the four waves stream neighbouring rows).  After the shuffle sum
+// every lane of a row holds that row's total, so lane g * 8 + r keeps the
+// own-row operands and results of row r of the wave's tile g: they are loaded
+// once when the wave starts and stored once when it ends, and no store is
+// outstanding inside the tile loop (a pending store would make every wait on
+// a gather wait for all outstanding loads, the next chunk's copy included).
+__global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+  __shared__ StreamLds sh;
+  // the stop flag is the same for every wave; it is tested once the first
+  // row pointers are in flight
+  const int stopped = a.check_stop ? load_stopped(a.slot) : 0;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = lane % kSR, g = lane / kSR;
+  const d2* v1 = reinterpret_cast<const d2*>(t1.val);
+  const d2* v2 = reinterpret_cast<const d2*>(t2.val);
+  const d2* x1 = reinterpret_cast<const d2*>(a.x1);
+  const d2* x2 = reinterpret_cast<const d2*>(a.x2);
+
+  auto tile_row0 = [&](int j) { return (L * kSW * kTPW + wv + j * kSW) * kSR; };
+  auto tile_rows = [&](int j) { return j < kTPW ? max(0, min(kSR, dim - tile_row0(j))) : 0; };
+  // row pointers of tile j: lanes 0..nr hold term 1's, lanes 32..32+nr term
+  // 2's; one unconditional load per lane (other lanes and tiles past the end
+  // read an entry that exists), so no copy has to wait for it
+  auto load_rp = [&](int j) {
+    const int nr = tile_rows(j);
+    const int idx = nr > 0 ? tile_row0(j) + min(lane & 31, nr) : 0;
+    const int* rp = lane < 32 ? t1.rp : t2.rp;
+    return rp[idx];
+  };
+  auto tile_of = [&](int j, int v) {
+    Tile T{tile_rows(j), 0, 0, 0, 0};
+    if (T.nr > 0) {
+      T.base1 = __builtin_amdgcn_readlane(v, 0);
+      T.n1 = __builtin_amdgcn_readlane(v, T.nr) - T.base1;
+      T.base2 = __builtin_amdgcn_readlane(v, 32);
+      T.total = T.n1 + __builtin_amdgcn_readlane(v, 32 + T.nr) - T.base2;
+    }
+    return T;
+  };
+  // copy entries [c0, c0 + 256) of tile T into buffer b; lanes past the end
+  // of the chunk re-read its first entry (always present) and are ignored
+  auto issue = [&](const Tile& T, int c0, int b) {
+    const int cn = min(kSCap, T.total - c0);
+#pragma unroll 1
+    for (int u = 0; u < kSU; ++u) {
+      if (u * 64 < cn) {
+        const int k = u * 64 + lane;
+        const int gk = c0 + (k < cn ? k : 0);
+        const bool first = gk < T.n1;
+        const int e = first ? T.base1 + gk : T.base2 + (gk - T.n1);
+        const d2* vp = (first ? v1 : v2) + e;
+        const int* cp = (first ? t1.ci : t2.ci) + e;
+        __builtin_amdgcn_global_load_lds(vp, (lds_void*)&sh.val[wv][b][u * 64], 16, 0, kNonTemporal);
+        __builtin_amdgcn_global_load_lds(cp, (lds_void*)&sh.col[wv][b][u * 64], 4, 0, kNonTemporal);
+      }
+    }
+  };
+
+  int rp_cur = load_rp(0);
+  int rp_nxt = load_rp(1);
+  // own-row operands of row r of tile g (rows past the end read row 0)
+  const int my_row = tile_row0(g) + r;
+  const bool my_valid = my_row < dim;
+  const int my_ld = my_valid ? my_row : 0;
+  const d2 w_old = tod2(a.wcur[my_ld]);
+  d2 p_old = {0.0, 0.0};
+  if (!a.first) p_old = tod2(a.pacc[my_ld]);
+  if (stopped) return;  // uniform over the workgroup
+
+  Tile T = tile_of(0, rp_cur);
+  int buf = 0;
+  if (T.total > 0) issue(T, 0, 0);
+  double pw = 0.0, pv = 0.0;
+  d2 res_w = {0.0, 0.0}, res_p = {0.0, 0.0};
+
+  for (int j = 0; j < kTPW && T.nr > 0; ++j) {
+    const Tile Tn = tile_of(j + 1, rp_nxt);
+    // this lane's entry ranges in the tile's entry stream
+    int s1 = 0, e1 = 0, s2 = 0, e2 = 0;
+    {
+      const int q0 = __shfl(rp_cur, r, 64), q1 = __shfl(rp_cur, r + 1, 64);
+      const int q2 = __shfl(rp_cur, 32 + r, 64), q3 = __shfl(rp_cur, 33 + r, 64);
+      if (r < T.nr) {
+        s1 = q0 - T.base1;
+        e1 = q1 - T.base1;
+        s2 = T.n1 + q2 - T.base2;
+        e2 = T.n1 + q3 - T.base2;
+      }
+    }
+    int rp_after = 0;
+    d2 acc1 = {0.0, 0.0}, acc2 = {0.0, 0.0};
+    int c0 = 0;
+    do {
+      const bool has = c0 < T.total;  // false only for a tile without entries
+      const int hi = min(T.total, c0 + kSCap);
+      const int nb = has ? buf ^ 1 : buf;  // where the next chunk goes
+      wait_vmem();  // this chunk is in LDS; every earlier access has completed
+      if (c0 == 0) rp_after = load_rp(j + 2);
+      // the next chunk: the rest of this tile, or the next tile's first
+      const bool more = has && hi < T.total;
+      bool issued = false;
+      auto issue_next = [&]() {
+        if (more) issue(T, hi, nb);
+        else if (Tn.total > 0) issue(Tn, 0, nb);
+        issued = true;
+      };
+      if (has) {
+        const int lo1 = max(s1, c0) + g, end1 = min(e1, hi);
+        const int lo2 = max(s2, c0) + g, end2 = min(e2, hi);
+        const unsigned vbase = lds_offset(&sh.val[wv][buf][0]), cbase = lds_offset(&sh.col[wv][buf][0]);
+        for (int q = 0;; ++q) {
+          const int b1 = lo1 + q * kNB * kSG, b2 = lo2 + q * kNB * kSG;
+          if (!__any(b1 < end1 || b2 < end2)) break;
+          // entry positions in the buffer, clamped into it for the lanes
+          // whose slots run past their row (those values are not used)
+          int k1[kNB], k2[kNB];
+#pragma unroll
+          for (int i = 0; i < kNB; ++i) {
+            k1[i] = min(b1 + i * kSG - c0, kSCap - 1);
+            k2[i] = min(b2 + i * kSG - c0, kSCap - 1);
+          }
+          int c1[kNB], c2[kNB];
+          {
+            unsigned ca1[kNB], ca2[kNB];
+#pragma unroll
+            for (int i = 0; i < kNB; ++i) {
+              ca1[i] = cbase + 4u * (unsigned)k1[i];
+              ca2[i] = cbase + 4u * (unsigned)k2[i];
+            }
+            lds_read_cols(ca1, ca2, c1, c2);
+          }
+          d2 g1[kNB], g2[kNB];
+#pragma unroll
+          for (int i = 0; i < kNB; ++i) {
+            g1[i] = x1[b1 + i * kSG < end1 ? c1[i] : 0];
+            g2[i] = x2[b2 + i * kSG < end2 ? c2[i] : 0];
+          }
+          // the next chunk's copy goes out behind this round's gathers, so
+          // waiting for the gathers does not wait for it
+          if (!issued) issue_next();
+          d2 h1[kNB], h2[kNB];
+          {
+            unsigned va1[kNB], va2[kNB];
+#pragma unroll
+            for (int i = 0; i < kNB; ++i) {
+              va1[i] = vbase + 16u * (unsigned)k1[i];
+              va2[i] = vbase + 16u * (unsigned)k2[i];
+            }
+            lds_read_vals(va1, va2, h1, h2);
+          }
+#pragma unroll
+          for (int i = 0; i < kNB; ++i)
+            if (b1 + i * kSG < end1) acc1 += cmul(h1[i], g1[i]);
+#pragma unroll
+          for (int i = 0; i < kNB; ++i)
+            if (b2 + i * kSG < end2) acc2 += cmul(h2[i], g2[i]);
+        }
+        buf = nb;
+      }
+      if (!issued) issue_next();
+      c0 += kSCap;
+    } while (c0 < T.total);
+#pragma unroll
+    for (int off = 32; off >= kSR; off >>= 1) {
+      acc1.x += __shfl_xor(acc1.x, off, 64);
+      acc1.y += __shfl_xor(acc1.y, off, 64);
+      acc2.x += __shfl_xor(acc2.x, off, 64);
+      acc2.y += __shfl_xor(acc2.y, off, 64);
+    }
+    // the lanes of slot j hold this tile's rows: the Leja update
+    if (g == j && r < T.nr) {
+      const d2 y = rmul(a.a1, acc1) + rmul(a.a2, acc2);
+      const d2 wn = y - rmul(a.sigma, w_old);
+      if (a.first) {
+        res_p = cmul(tod2(a.d0), w_old) + cmul(tod2(a.d), wn);
+        pv += nrm2(w_old);
+      } else {
+        res_p = p_old + cmul(tod2(a.d), wn);
+      }
+      res_w = wn;
+      pw += nrm2(wn);
+    }
+    rp_cur = rp_nxt;
+    rp_nxt = rp_after;
+    T = Tn;
+  }
+  if (my_valid) {
+    a.wout[my_row] = fromd2(res_w);
+    a.pacc[my_row] = fromd2(res_p);
+  }
+  wait_vmem();  // no copy into this wave's buffers is still in flight
+  pw = wave_sum(pw);
+  pv = wave_sum(pv);
+  double* red = reinterpret_cast<double*>(&sh.val[wv][0][0]);  // this wave's own buffer
+  if (lane == 0) {
+    red[0] = pw;
+    red[1] = pv;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double bw = 0.0, bv = 0.0;
+    for (int k = 0; k < kSW; ++k) {
+      const double* rk = reinterpret_cast<const double*>(&sh.val[k][0][0]);
+      bw += rk[0];
+      bv += rk[1];
+    }
+    a.partials[blockIdx.x] = bw;
+    if (a.first) a.partials[gridDim.x + blockIdx.x] = bv;
+  }
+}
+
+}  // namespace
+
+int csr2_stream_grid(int dim) {
+  const long long rows = (long long)kSR * kSW * kTPW;
+  return (int)std::max<long long>(1, (dim + rows - 1) / rows);
+}
+
+hipError_t launch_csr2_stream(const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a, hipStream_t s) {
+  csr2_stream_kernel<<<csr2_stream_grid(dim), kThreads, 0, s>>>(t1, t2, dim, a);
+  return hipGetLastError();
+}
+
+}  // namespace magnus

@@ -321,11 +321,11 @@ def test_nan_state_reported(ctx, chain10):
     ctx.check()
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_csr_kernel_variants_match_oracle(variant, monkeypatch):
     """Every CSR iteration kernel (nonzero-streaming 16/64-row blocks, row-per-lane
-    32/64/128-row blocks, wave tiles of 8/16 rows) on irregular rows (empty rows, rows longer than one
-    LDS chunk) and a ragged tail, in Leja and commutator modes."""
+    32/64/128-row blocks, wave tiles of 8/16 rows, streamed wave tiles) on irregular rows (empty rows, rows longer than one LDS chunk) and a ragged tail, in
+    Leja and commutator modes."""
     monkeypatch.setenv("MAGNUS_CSR_VARIANT", str(variant))
     N = 70001
     H1 = _ragged_hermitian(N, 41, long_rows=(0, 5, N - 1), long_len=6000)
@@ -671,3 +671,29 @@ def test_small_state_path_selection(n, batch, persistent, monkeypatch):
                        expm="taylor")
     assert rel(out[batch - 1], ref) <= BUDGET
     c.close()
+
+
+@pytest.mark.parametrize("variant", ["7"])
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 17, 130, 1000, 5000])
+def test_streamed_tiles_small_and_degenerate(N, variant, monkeypatch):
+    """The streamed wave-tile kernel on dimensions that leave most tiles and waves of a
+    workgroup empty, rows without entries and an H2 without entries (null arrays):
+    it matches the oracle and the 8-row wave-tile kernel, which sums in the same order."""
+    import scipy.sparse as sp
+    H1, A1 = _tiny_hermitian(N, seed=1900 + N, density=0.5 if N <= 130 else 0.02,
+                             empty_rows=(N // 2,) if N > 2 else ())
+    H2z = inputs.CSR(np.zeros(N + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, complex), N)
+    H2, A2 = _tiny_hermitian(N, seed=1950 + N, density=0.3 if N <= 130 else 0.01)
+    v = inputs.random_states(N, seed=1960 + N)
+    tol = 1e-12
+    for second, A2d in ((H2z, np.zeros((N, N))), (H2, A2)):
+        out = {}
+        for var in (variant, "5"):
+            monkeypatch.setenv("MAGNUS_CSR_VARIANT", var)
+            c = B.Context(max_dim=N)
+            ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, second))
+            out[var] = host(B.expmv_leja(c, ham, 0.7, -0.3, 0.0, 0.05, dev(v), opts=B.leja_opts(tol)))
+            c.close()
+        ref = oe.expmv_taylor(oracle_exponent(sp.csr_matrix(A1), sp.csr_matrix(A2d), 0.7, -0.3, 0.0, 0.05), v)
+        assert rel(out[variant], ref) <= 20 * tol, N
+        assert rel(out[variant], out["5"]) <= 1e-14, N
