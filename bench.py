@@ -243,24 +243,29 @@ CSR_KERNEL_NAMES = {0: "csr2_wave_kernel<8, kLeja>", 1: "csr2_iter_kernel<64, kL
                     7: "csr2_stream_kernel"}
 
 
-def kernel_source_digest(sources=None) -> str:
-    """sha256 over the source text the CSR iteration kernel is compiled from: its own
-    definition in kernels.hip, the structs it takes (kernels.h) and the device helpers
-    (device_common.h).  Counters taken from another version of these do not apply."""
+def kernel_source_digest(kernel: str = "csr2_wave_kernel<8, kLeja>", sources=None) -> str:
+    """sha256 over the source text a CSR iteration kernel is compiled from: its own
+    definition (the wave-tile kernel's template in kernels.hip; the whole of
+    kernels_stream.hip for the streamed kernel), the structs it takes (kernels.h) and
+    the device helpers (device_common.h).  Counters taken from another version of
+    these do not apply."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_1709_06483_amd", "csrc")
     if sources is None:
         sources = {}
-        for name in ("kernels.hip", "kernels.h", "device_common.h"):
+        for name in ("kernels.hip", "kernels_stream.hip", "kernels.h", "device_common.h"):
             with open(os.path.join(csrc, name)) as fh:
                 sources[name] = fh.read()
-    k = sources["kernels.hip"]
-    i = k.index("void csr2_wave_kernel(")
-    i = k.rindex("template <int RPW, int MODE>", 0, i)
-    j = k.index("\n// ----", i)
     h = hashlib.sha256()
-    h.update(k[i:j].encode())
+    if kernel.startswith("csr2_stream_kernel"):
+        h.update(sources["kernels_stream.hip"].encode())
+    else:
+        k = sources["kernels.hip"]
+        i = k.index("void csr2_wave_kernel(")
+        i = k.rindex("template <int RPW, int MODE>", 0, i)
+        j = k.index("\n// ----", i)
+        h.update(k[i:j].encode())
     for struct in ("Slot", "CsrDev", "IterArgs"):
         m = re.search(r"struct %s \{.*?\n\};" % struct, sources["kernels.h"], re.S)
         h.update(m.group(0).encode())
@@ -272,7 +277,7 @@ def recorded_traffic(kernel: str, workload: str):
     """HBM bytes per launch from a committed counter summary (a line
     'traffic-record: {json}' in profiles/*.md) taken on the current kernel source,
     else None."""
-    digest = kernel_source_digest()
+    digest = kernel_source_digest(kernel)
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None

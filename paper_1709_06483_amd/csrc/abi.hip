@@ -106,8 +106,9 @@ struct magnus_ctx {
   std::set<std::tuple<const void*, const void*, const void*, int64_t, int64_t>> validated;
   std::mutex mu;
   // kernel timing: (kind, start, stop) per recorded launch, events reused from a pool
-  int csr_variant = 0;  // MAGNUS_CSR_VARIANT: 0 auto (wave tiles of 8 rows from 65536 rows on),
-                        // 1 nonzero-streaming, 2-4 row-per-lane (64/32/128 rows), 5-6 wave tiles (8/16 rows)
+  int csr_variant = 0;  // MAGNUS_CSR_VARIANT: 0 auto (wave tiles of 8 rows from 65536 rows on, streamed
+                        // wave tiles from 262144), 1 nonzero-streaming, 2-4 row-per-lane (64/32/128 rows),
+                        // 5-6 wave tiles (8/16 rows), 7 streamed wave tiles
   // magnus_autotune results, per CSR term pair (H1 row_ptr, dim): the variant code
   // of the single-state iteration and the states per multi-state pass
   std::map<std::pair<const void*, int64_t>, int> tuned_variant, tuned_group;
@@ -276,7 +277,10 @@ int variant_rows(int code, int64_t dim) {
     case 5: return magnus::kWaveTile + 8;
     case 6: return magnus::kWaveTile + 16;
     case 7: return magnus::kStreamTile;
-    default: return dim >= 65536 ? magnus::kWaveTile + 8 : 16;
+    // measured on spin chains: the streamed tiles win from 2^18 rows on (n = 18:
+    // 42 vs 48 us, n = 20: 169 vs 183 us) and lose below 2^17, where the grid
+    // leaves compute units idle while each wave walks its 8 tiles in turn
+    default: return dim >= 262144 ? magnus::kStreamTile : dim >= 65536 ? magnus::kWaveTile + 8 : 16;
   }
 }
 

@@ -1,17 +1,16 @@
 // Two-term CSR Leja iteration (Section 3's recurrence on a1 H1 + a2 H2), the
 // streaming wave-tile variant.
 //
-// Every wave walks `tpw` tiles of 8 consecutive rows.  A tile's column indices
-// and values (term 1's entries of its rows, then term 2's) travel from HBM
+// Every wave walks 8 tiles of 8 consecutive rows.  A tile's column indices and
+// values (term 1's entries of its rows, then term 2's) travel from HBM
 // straight into a wave-private LDS buffer with global_load_lds (no VGPRs held
-// while in flight).  Each chunk of 256 entries is copied one step ahead: the
-// copy of the next chunk, the tile's own-row operands, the row pointers two
-// tiles ahead and the previous tile's results are all issued before the
-// gathers of the current chunk, so the wave waits once per chunk for all of
-// them together instead of once per dependent step (row pointers, then the
-// entries, then the gathers).  Lanes are laid out row-fastest (lane = g * 8 +
-// r) and each row's 8 groups are summed with shuffles in a fixed order, the
-// same order and chunking as the 8-row wave-tile kernel.
+// while in flight), one chunk of 256 entries ahead of the chunk being
+// processed.  Per chunk the wave waits once: the copy of the chunk, issued
+// during the previous one, and the row pointers two tiles ahead have arrived;
+// it then reads its entries' columns, issues the gathers, issues the copy of
+// the next chunk behind them, and multiplies.  Lanes are laid out row-fastest
+// (lane = g * 8 + r) and each row's 8 groups are summed with shuffles in a
+// fixed order, the same order and chunking as the 8-row wave-tile kernel.
 //
 // The LDS reads of staged entries are inline ds_read instructions followed by
 // their own lgkmcnt wait: the compiler would otherwise make every LDS read wait
