@@ -38,6 +38,16 @@ constexpr int kSU = kSCap / 64;     // copy instructions per buffer and array
 constexpr int kNB = 3;              // entries per lane and term in one gather round
 constexpr int kTPW = kSG;           // tiles per wave: one per lane slot g
 constexpr unsigned kNonTemporal = 2;  // cache policy of the matrix stream (nt)
+// The matrix is read again by every iteration.  Copied with non-temporal
+// loads it never stays in the 256 MiB memory-side cache (MALL) of MI355X,
+// and copied with normal loads it evicts itself before it is read again; so
+// the tiles at the front of the matrix, up to what the MALL holds besides the
+// vectors an iteration touches (about 80 bytes per row: x, w and p read, w
+// and p written), use normal loads and stay resident from one iteration to
+// the next, and the rest stream through.  Measured on spin chains (us per
+// iteration, none / 96 / 160 / 224 MB kept): n = 20 168 / 164 / 158 / 161,
+// n = 19 84 / 77 / 76 / 74.
+constexpr long long kMallKeepBytes = 240LL << 20;
 
 // Wave-private double buffers: 2 x (256 values + 256 column indices) per wave,
 // 40 KiB per workgroup, so four workgroups (16 waves) share a CU's LDS.
@@ -99,7 +109,8 @@ struct Tile {
 // once when the wave starts and stored once when it ends, and no store is
 // outstanding inside the tile loop (a pending store would make every wait on
 // a gather wait for all outstanding loads, the next chunk's copy included).
-__global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+__global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a,
+                                                                  int keep_entries) {
   __shared__ StreamLds sh;
   // the stop flag is the same for every wave; it is tested once the first
   // row pointers are in flight
@@ -135,9 +146,12 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
     return T;
   };
   // copy entries [c0, c0 + 256) of tile T into buffer b; lanes past the end
-  // of the chunk re-read its first entry (always present) and are ignored
+  // of the chunk re-read its first entry (always present) and are ignored.
+  // Tiles whose entries start within the first keep_entries of the two
+  // terms together are copied with normal loads, the others non-temporal.
   auto issue = [&](const Tile& T, int c0, int b) {
     const int cn = min(kSCap, T.total - c0);
+    const bool keep = T.base1 + T.base2 < keep_entries;
 #pragma unroll 1
     for (int u = 0; u < kSU; ++u) {
       if (u * 64 < cn) {
@@ -147,8 +161,13 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
         const int e = first ? T.base1 + gk : T.base2 + (gk - T.n1);
         const d2* vp = (first ? v1 : v2) + e;
         const int* cp = (first ? t1.ci : t2.ci) + e;
-        __builtin_amdgcn_global_load_lds(vp, (lds_void*)&sh.val[wv][b][u * 64], 16, 0, kNonTemporal);
-        __builtin_amdgcn_global_load_lds(cp, (lds_void*)&sh.col[wv][b][u * 64], 4, 0, kNonTemporal);
+        if (keep) {
+          __builtin_amdgcn_global_load_lds(vp, (lds_void*)&sh.val[wv][b][u * 64], 16, 0, 0);
+          __builtin_amdgcn_global_load_lds(cp, (lds_void*)&sh.col[wv][b][u * 64], 4, 0, 0);
+        } else {
+          __builtin_amdgcn_global_load_lds(vp, (lds_void*)&sh.val[wv][b][u * 64], 16, 0, kNonTemporal);
+          __builtin_amdgcn_global_load_lds(cp, (lds_void*)&sh.col[wv][b][u * 64], 4, 0, kNonTemporal);
+        }
       }
     }
   };
@@ -314,7 +333,10 @@ int csr2_stream_grid(int dim) {
 }
 
 hipError_t launch_csr2_stream(const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a, hipStream_t s) {
-  csr2_stream_kernel<<<csr2_stream_grid(dim), kThreads, 0, s>>>(t1, t2, dim, a);
+  // entries (20 bytes each, both terms) kept resident in the MALL
+  const long long keep = std::max(0LL, kMallKeepBytes - 80LL * dim) / 20;
+  const int keep_entries = (int)std::min<long long>(keep, 1LL << 30);
+  csr2_stream_kernel<<<csr2_stream_grid(dim), kThreads, 0, s>>>(t1, t2, dim, a, keep_entries);
   return hipGetLastError();
 }
 
