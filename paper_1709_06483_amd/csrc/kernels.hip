@@ -10,7 +10,9 @@
 // host never waits.
 #include "kernels.h"
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace magnus {
 namespace {
@@ -567,9 +569,12 @@ __global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave
 // transaction, and each gathered x_j is loaded once per lane for RPW rows and
 // both terms.
 // ---------------------------------------------------------------------------
+// Rows below keep_rows are read with normal loads so that they stay in the
+// memory-side cache (MALL) from one iteration to the next (the matrix is read
+// again by every iteration); the rest stream through non-temporally.
 template <int RPW, int NT>
 __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1, const double2* H2,
-                                                              int dim, long long ld, IterArgs a) {
+                                                              int dim, long long ld, IterArgs a, int keep_rows) {
   if (a.check_stop && load_stopped(a.slot)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -584,23 +589,32 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
   if (nr < 0) nr = 0;
   // columns in groups of UNR per lane: the same matrix bytes in flight per wave for one term or two
   constexpr int UNR = NT == 2 ? 2 : 4;
-  for (int j0 = lane; j0 < dim; j0 += 64 * UNR) {
+  auto run = [&](auto streaming) {
+    for (int j0 = lane; j0 < dim; j0 += 64 * UNR) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int j = j0 + 64 * u;
-      if (j < dim) {
-        const d2 xj = x[j];
+      for (int u = 0; u < UNR; ++u) {
+        const int j = j0 + 64 * u;
+        if (j < dim) {
+          const d2 xj = x[j];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          if (r < nr) {
-            const long long off = (long long)(rbase + r) * ld + j;
-            acc1[r] += cmul(__builtin_nontemporal_load(A1 + off), xj);
-            if constexpr (NT == 2) acc2[r] += cmul(__builtin_nontemporal_load(A2 + off), xj);
+          for (int r = 0; r < RPW; ++r) {
+            if (r < nr) {
+              const long long off = (long long)(rbase + r) * ld + j;
+              if constexpr (decltype(streaming)::value) {
+                acc1[r] += cmul(__builtin_nontemporal_load(A1 + off), xj);
+                if constexpr (NT == 2) acc2[r] += cmul(__builtin_nontemporal_load(A2 + off), xj);
+              } else {
+                acc1[r] += cmul(A1[off], xj);
+                if constexpr (NT == 2) acc2[r] += cmul(A2[off], xj);
+              }
+            }
           }
         }
       }
     }
-  }
+  };
+  if (rbase < keep_rows) run(std::false_type{});
+  else run(std::true_type{});
   double pw = 0.0, pv = 0.0;
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
@@ -790,10 +804,17 @@ int dense2_grid(int dim, int nterms) {
   return (dim + rows_per_block - 1) / rows_per_block;
 }
 
+// MALL budget kept for matrix rows: its 256 MiB less a margin and the vectors
+// an iteration touches (x, w and p read, w and p written).
+constexpr long long kDenseMallKeepBytes = 240LL << 20;
+
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s) {
-  if (H2) dense2_iter_kernel<kDenseRPW2, 2><<<dense2_grid(dim, 2), kThreads, 0, s>>>(H1, H2, dim, ld, a);
-  else dense2_iter_kernel<kDenseRPW1, 1><<<dense2_grid(dim, 1), kThreads, 0, s>>>(H1, H1, dim, ld, a);
+  const long long row_bytes = 16LL * ld * (H2 ? 2 : 1);
+  const long long keep = std::max(0LL, kDenseMallKeepBytes - 80LL * dim) / std::max(1LL, row_bytes);
+  const int keep_rows = (int)std::min<long long>(keep, dim);
+  if (H2) dense2_iter_kernel<kDenseRPW2, 2><<<dense2_grid(dim, 2), kThreads, 0, s>>>(H1, H2, dim, ld, a, keep_rows);
+  else dense2_iter_kernel<kDenseRPW1, 1><<<dense2_grid(dim, 1), kThreads, 0, s>>>(H1, H1, dim, ld, a, keep_rows);
   return hipGetLastError();
 }
 
