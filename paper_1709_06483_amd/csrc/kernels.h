@@ -75,6 +75,11 @@ hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int di
 // Grid size (workgroups) of launch_csr2_iter for `dim` rows.
 int csr2_grid(int dim, int rows_per_block);
 
+// CSR entries (both terms, from the start of the matrix) that the iteration
+// kernels read with normal loads so that they stay in the 256 MiB MALL from
+// one pass over the matrix to the next; the rest are read non-temporally.
+int csr_keep_entries(int dim);
+
 // The streaming kernel (kernels_stream.hip).
 hipError_t launch_csr2_stream(const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a, hipStream_t s);
 int csr2_stream_grid(int dim);

@@ -411,8 +411,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Seven waves per SIMD (at most 72 VGPRs): enough independent tiles in flight
 // per CU to cover the memory latency of each tile's load -> gather chain.  The
 // commutator pass holds two more own-row vectors and gets six (no spills).
+// keep_entries: tiles whose entries start within the first keep_entries of the
+// two terms together are read with normal loads, so that they stay in the
+// memory-side cache (MALL) until the next pass over the matrix; the rest are
+// read non-temporally.
 template <int RPW, int MODE>
-__global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+__global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a,
+                                                                                      int keep_entries) {
   constexpr int NWAVE = kThreads / 64;
   constexpr int G = 64 / RPW;      // entry groups per row
   constexpr int CAPW = RPW * 32;   // entries staged per chunk
@@ -474,26 +479,35 @@ __global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave
     const d2* v1 = reinterpret_cast<const d2*>(t1.val);
     const d2* v2 = reinterpret_cast<const d2*>(t2.val);
     d2 acc1 = {0.0, 0.0}, acc2 = {0.0, 0.0};
+    const bool keep = base1 + base2 < keep_entries;  // uniform over the wave
     for (int c0 = 0; c0 < total; c0 += CAPW) {
       const int cn = min(CAPW, total - c0);
       int col[U];
       d2 val[U];
+      auto load_chunk = [&](auto streaming) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = u * 64 + lane;
-        const int gk = c0 + k;
-        col[u] = 0;
-        val[u] = d2{0.0, 0.0};
-        if (k < cn) {
-          if (gk < n1) {
-            col[u] = __builtin_nontemporal_load(t1.ci + base1 + gk);
-            val[u] = __builtin_nontemporal_load(v1 + base1 + gk);
-          } else {
-            col[u] = __builtin_nontemporal_load(t2.ci + base2 + (gk - n1));
-            val[u] = __builtin_nontemporal_load(v2 + base2 + (gk - n1));
+        for (int u = 0; u < U; ++u) {
+          const int k = u * 64 + lane;
+          const int gk = c0 + k;
+          col[u] = 0;
+          val[u] = d2{0.0, 0.0};
+          auto ld = [&](const auto* p) {
+            if constexpr (decltype(streaming)::value) return __builtin_nontemporal_load(p);
+            else return *p;
+          };
+          if (k < cn) {
+            if (gk < n1) {
+              col[u] = ld(t1.ci + base1 + gk);
+              val[u] = ld(v1 + base1 + gk);
+            } else {
+              col[u] = ld(t2.ci + base2 + (gk - n1));
+              val[u] = ld(v2 + base2 + (gk - n1));
+            }
           }
         }
-      }
+      };
+      if (keep) load_chunk(std::false_type{});
+      else load_chunk(std::true_type{});
       wave_lds_sync();  // the previous chunk's LDS reads are done
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -732,6 +746,13 @@ __global__ void slot_reset_kernel(Slot* s, int n) {
 
 }  // namespace
 
+int csr_keep_entries(int dim) {
+  // the MALL's 256 MiB less a margin and the vectors an iteration touches
+  // (about 80 bytes per row), in 20-byte CSR entries
+  const long long keep = std::max(0LL, (240LL << 20) - 80LL * dim) / 20;
+  return (int)std::min<long long>(keep, 1LL << 30);
+}
+
 int csr2_grid(int dim, int rows_per_block) {
   if (rows_per_block == kStreamTile) return csr2_stream_grid(dim);
   int rows = rows_per_block < 0 ? -rows_per_block : rows_per_block;
@@ -770,9 +791,10 @@ hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int di
 #define MAGNUS_WAVE_CASE(R)                                                                         \
   if (rows_per_block == kWaveTile + R) {                                                            \
     const int g = csr2_grid(dim, rows_per_block);                                                   \
-    if (mode == kLeja) csr2_wave_kernel<R, kLeja><<<g, kThreads, 0, s>>>(t1, t2, dim, a);           \
-    else if (mode == kSplit) csr2_wave_kernel<R, kSplit><<<g, kThreads, 0, s>>>(t1, t2, dim, a);    \
-    else csr2_wave_kernel<R, kLejaComm><<<g, kThreads, 0, s>>>(t1, t2, dim, a);                     \
+    const int ke = csr_keep_entries(dim);                                                           \
+    if (mode == kLeja) csr2_wave_kernel<R, kLeja><<<g, kThreads, 0, s>>>(t1, t2, dim, a, ke);       \
+    else if (mode == kSplit) csr2_wave_kernel<R, kSplit><<<g, kThreads, 0, s>>>(t1, t2, dim, a, ke); \
+    else csr2_wave_kernel<R, kLejaComm><<<g, kThreads, 0, s>>>(t1, t2, dim, a, ke);                 \
     return hipGetLastError();                                                                       \
   }
   MAGNUS_WAVE_CASE(8)

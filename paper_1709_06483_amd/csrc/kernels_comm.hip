@@ -12,6 +12,7 @@
 // 8 lanes per row, each tile's entries of the three terms staged in LDS
 // with coalesced non-temporal loads, fixed-order shuffle sums).
 #include <climits>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -111,8 +112,8 @@ __global__ __launch_bounds__(kCommWaves * 64) void csr_commutator_kernel(CsrDev 
 // ---------------------------------------------------------------------------
 constexpr int kRPW3 = 8;
 
-__global__ __launch_bounds__(kThreads, 6) void csr3_wave_kernel(CsrDev t1, CsrDev t2, CsrDev t3, int dim, IterArgs a,
-                                                               double a3) {
+__global__ __launch_bounds__(kThreads, 5) void csr3_wave_kernel(CsrDev t1, CsrDev t2, CsrDev t3, int dim, IterArgs a,
+                                                               double a3, int keep_entries) {
   constexpr int NWAVE = kThreads / 64;
   constexpr int RPW = kRPW3;
   constexpr int G = 64 / RPW;
@@ -169,29 +170,40 @@ __global__ __launch_bounds__(kThreads, 6) void csr3_wave_kernel(CsrDev t1, CsrDe
     const d2* v2 = reinterpret_cast<const d2*>(t2.val);
     const d2* v3 = reinterpret_cast<const d2*>(t3.val);
     d2 acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    // the front of the matrix is read with normal loads and stays in the MALL
+    // until the next iteration; the rest streams through (uniform per wave)
+    const bool keep = base[0] + base[1] + base[2] < keep_entries;
     for (int c0 = 0; c0 < total; c0 += CAPW) {
       const int cn = min(CAPW, total - c0);
       int col[U];
       d2 val[U];
+      auto load_chunk = [&](auto streaming) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = u * 64 + lane;
-        const int gk = c0 + k;
-        col[u] = 0;
-        val[u] = d2{0.0, 0.0};
-        if (k < cn) {
-          if (gk < off2) {
-            col[u] = __builtin_nontemporal_load(t1.ci + base[0] + gk);
-            val[u] = __builtin_nontemporal_load(v1 + base[0] + gk);
-          } else if (gk < off3) {
-            col[u] = __builtin_nontemporal_load(t2.ci + base[1] + (gk - off2));
-            val[u] = __builtin_nontemporal_load(v2 + base[1] + (gk - off2));
-          } else {
-            col[u] = __builtin_nontemporal_load(t3.ci + base[2] + (gk - off3));
-            val[u] = __builtin_nontemporal_load(v3 + base[2] + (gk - off3));
+        for (int u = 0; u < U; ++u) {
+          const int k = u * 64 + lane;
+          const int gk = c0 + k;
+          col[u] = 0;
+          val[u] = d2{0.0, 0.0};
+          auto ld = [&](const auto* p) {
+            if constexpr (decltype(streaming)::value) return __builtin_nontemporal_load(p);
+            else return *p;
+          };
+          if (k < cn) {
+            if (gk < off2) {
+              col[u] = ld(t1.ci + base[0] + gk);
+              val[u] = ld(v1 + base[0] + gk);
+            } else if (gk < off3) {
+              col[u] = ld(t2.ci + base[1] + (gk - off2));
+              val[u] = ld(v2 + base[1] + (gk - off2));
+            } else {
+              col[u] = ld(t3.ci + base[2] + (gk - off3));
+              val[u] = ld(v3 + base[2] + (gk - off3));
+            }
           }
         }
-      }
+      };
+      if (keep) load_chunk(std::false_type{});
+      else load_chunk(std::true_type{});
       comm_lds_sync();  // the previous chunk's LDS reads are done
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -261,7 +273,7 @@ int csr3_grid(int dim) {
 
 hipError_t launch_csr3_iter(const CsrDev& t1, const CsrDev& t2, const CsrDev& t3, int dim, const IterArgs& a,
                             double a3, hipStream_t s) {
-  csr3_wave_kernel<<<csr3_grid(dim), kThreads, 0, s>>>(t1, t2, t3, dim, a, a3);
+  csr3_wave_kernel<<<csr3_grid(dim), kThreads, 0, s>>>(t1, t2, t3, dim, a, a3, csr_keep_entries(dim));
   return hipGetLastError();
 }
 
