@@ -308,9 +308,8 @@ typedef struct {
  * sizes (the one-step scheme of Section 2 on each).  CSR problems of the
  * product-of-exponentials methods (Cf4, Cf4:3, M2) run in persistent launches
  * (one workgroup per state carries every step with its vectors in LDS; up to
- * 256 or max_batch states per launch) when their dimension is within the
- * cap stated at propagate, for a state count taken over all CSR problems of
- * dimension at most 4096 in the call;
+ * 256 or max_batch states per launch) when their dimension is at most 4096
+ * (none with MAGNUS_PERSIST=0);
  * the others run first, as batched propagations, each followed by a host
  * wait that reports a non-finite norm (ENAN) at once.  Tolerances as in
  * propagate (tol_mode 1: budget over the exponentials of each state).

@@ -1709,12 +1709,12 @@ int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_
   std::vector<const magnus_hamiltonian*> hs;
   std::vector<SmallState> sst;
   std::vector<int> big;
-  int64_t ncand = 0;  // states that could share the persistent launches
-  for (int32_t i = 0; i < nprob; ++i)
-    if (!S.commutator && small_candidate(&probs[i].h)) ncand += probs[i].batch;
+  // every CSR problem of at most kSmallDim rows joins the persistent launches:
+  // the alternative here is a batched propagation per problem with a host
+  // wait after it, which costs more than the single-call crossover assumes
   for (int32_t i = 0; i < nprob; ++i) {
     const magnus_problem& P = probs[i];
-    if (!S.commutator && small_ok(ctx, &P.h, ncand)) {
+    if (!S.commutator && small_ok(ctx, &P.h, std::max<int64_t>(32, P.batch))) {
       const int pi = (int)hs.size();
       hs.push_back(&P.h);
       double2* psi = reinterpret_cast<double2*>(P.psi);

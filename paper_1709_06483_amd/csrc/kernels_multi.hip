@@ -9,6 +9,7 @@
 // [[H, H2], [0, H]], whose exponential carries the Frechet derivative of the
 // matrix exponential in its upper-right block.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -17,8 +18,12 @@ namespace {
 
 using namespace dev;
 
+// keep_entries: tiles whose entries start within the first keep_entries of the
+// two terms are read with normal loads (they stay in the MALL until the next
+// iteration), the rest non-temporally.
 template <int B, int MODE>
-__global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev t2, int dim, MultiArgs a) {
+__global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev t2, int dim, MultiArgs a,
+                                                             int keep_entries) {
   constexpr int NWAVE = kThreads / 64;
   constexpr int RP = 64 / B;                // rows per pass: lane = rr * B + b
   constexpr int RPW = RP;                   // rows per wave: one pass (with many states the
@@ -64,26 +69,35 @@ __global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev 
     const int base1 = srp[wv][0][0], n1 = srp[wv][0][nrows] - base1;
     const int base2 = srp[wv][1][0], n2 = srp[wv][1][nrows] - base2;
     const int total = n1 + n2;
+    const bool keep = base1 + base2 < keep_entries;  // uniform over the wave
     for (int c0 = 0; c0 < total; c0 += CAPW) {
       const int cn = min(CAPW, total - c0);
       int col[U];
       d2 val[U];
+      auto load_chunk = [&](auto streaming) {
+        auto ld = [&](const auto* p) {
+          if constexpr (decltype(streaming)::value) return __builtin_nontemporal_load(p);
+          else return *p;
+        };
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = u * 64 + lane;
-        const int gk = c0 + k;
-        col[u] = 0;
-        val[u] = d2{0.0, 0.0};
-        if (k < cn) {
-          if (gk < n1) {
-            col[u] = __builtin_nontemporal_load(t1.ci + base1 + gk);
-            val[u] = __builtin_nontemporal_load(v1 + base1 + gk);
-          } else {
-            col[u] = __builtin_nontemporal_load(t2.ci + base2 + (gk - n1));
-            val[u] = __builtin_nontemporal_load(v2 + base2 + (gk - n1));
+        for (int u = 0; u < U; ++u) {
+          const int k = u * 64 + lane;
+          const int gk = c0 + k;
+          col[u] = 0;
+          val[u] = d2{0.0, 0.0};
+          if (k < cn) {
+            if (gk < n1) {
+              col[u] = ld(t1.ci + base1 + gk);
+              val[u] = ld(v1 + base1 + gk);
+            } else {
+              col[u] = ld(t2.ci + base2 + (gk - n1));
+              val[u] = ld(v2 + base2 + (gk - n1));
+            }
           }
         }
-      }
+      };
+      if (keep) load_chunk(std::false_type{});
+      else load_chunk(std::true_type{});
       wave_lds_sync();  // the previous chunk's LDS reads are done
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -394,17 +408,20 @@ hipError_t launch_csr2_multi(int mode, const CsrDev& t1, const CsrDev& t2, int d
                              hipStream_t s) {
   const int grid = csr2_multi_grid(dim, a.B);
   if (grid <= 0) return hipErrorInvalidValue;
+  // the MALL's 256 MiB less a margin and the vectors of all B states
+  const long long keep = std::max(0LL, (240LL << 20) - 80LL * dim * a.B) / 20;
+  const int ke = (int)std::min<long long>(keep, 1LL << 30);
   if (mode == kMultiFrechet) {
     if (a.B != 2) return hipErrorInvalidValue;
-    csr2_multi_kernel<2, kMultiFrechet><<<grid, kThreads, 0, s>>>(t1, t2, dim, a);
+    csr2_multi_kernel<2, kMultiFrechet><<<grid, kThreads, 0, s>>>(t1, t2, dim, a, ke);
     return hipGetLastError();
   }
   switch (a.B) {
-    case 2: csr2_multi_kernel<2, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); break;
-    case 4: csr2_multi_kernel<4, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); break;
-    case 8: csr2_multi_kernel<8, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); break;
-    case 16: csr2_multi_kernel<16, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); break;
-    case 32: csr2_multi_kernel<32, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); break;
+    case 2: csr2_multi_kernel<2, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a, ke); break;
+    case 4: csr2_multi_kernel<4, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a, ke); break;
+    case 8: csr2_multi_kernel<8, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a, ke); break;
+    case 16: csr2_multi_kernel<16, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a, ke); break;
+    case 32: csr2_multi_kernel<32, kMultiLeja><<<grid, kThreads, 0, s>>>(t1, t2, dim, a, ke); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

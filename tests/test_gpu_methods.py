@@ -105,11 +105,10 @@ def test_dense_single_and_group(method):
     c.close()
 
 
-@pytest.mark.parametrize("persist", ["1", "2"])
+@pytest.mark.parametrize("persist", ["1", "0"])
 def test_ragged_cf43(persist, monkeypatch):
-    """Cf4:3 on chains of 8, 12 and 13 spins: the 8-spin states in one persistent
-    launch, the 13-spin chain batched, the 12-spin one batched by the size rule
-    (persist 1) or persistent (persist 2)."""
+    """Cf4:3 on chains of 8, 12 and 13 spins: the 8- and 12-spin states in one
+    persistent launch, the 13-spin chain batched (persist 0: all batched)."""
     monkeypatch.setenv("MAGNUS_PERSIST", persist)
     tau, nsteps = 0.01, 10
     c = B.Context(max_dim=1 << 13, max_batch=2)

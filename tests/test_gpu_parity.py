@@ -441,12 +441,11 @@ def test_small_state_propagation_paths_agree(persist, monkeypatch):
     c.close()
 
 
-@pytest.mark.parametrize("persist", ["1", "2"])
+@pytest.mark.parametrize("persist", ["1", "0"])
 def test_ragged_batch_matches_oracle(persist, monkeypatch):
-    """Chains of 8, 10, 12 and 15 spins with several states each, one call.  With
-    the size rule (persist 1, nine small states: cap 2048) the 8- and 10-spin
-    problems share one persistent launch and the 12- and 15-spin chains run
-    batched; with persist 2 the 12-spin chain joins the persistent launch."""
+    """Chains of 8, 10, 12 and 15 spins with several states each, one call: the
+    three problems of at most 4096 rows share one persistent launch and the
+    15-spin chain runs batched (persist 0: every problem runs batched)."""
     monkeypatch.setenv("MAGNUS_PERSIST", persist)
     tau, nsteps = 0.01, 12
     c = B.Context(max_dim=1 << 15, max_batch=4)
