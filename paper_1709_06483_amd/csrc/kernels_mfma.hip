@@ -10,6 +10,8 @@
 // A wave computes a 16 x 32 output tile (1 x 2 MFMA tiles), a workgroup of
 // four waves 32 rows x 64 states; K is staged through LDS 16 at a time with
 // the next chunk prefetched into registers while the MFMAs run.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace magnus {
@@ -21,17 +23,28 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int TM = 32, TN = 64, TK = 16;
 constexpr int WM = 16, WN = 32;   // wave tile
 constexpr int TJ = WN / 16;       // MFMA tiles per wave along the states
+// K is split between KS groups of four waves: group g accumulates the K
+// chunks g, g + KS, ... of the workgroup's tile in its own LDS slice, and the
+// groups' accumulators are added in a fixed order at the end.  A 32 x 64 tile
+// per workgroup leaves few workgroups for the chip (512 at 4096 rows and 256
+// states); the split gives each SIMD four waves to overlap the MFMA chains
+// with the staging of the next chunk.
+constexpr int KS = 2;
+constexpr int kMfmaThreads = KS * kThreads;
 
 template <int NT>
-__global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2* H1, const double2* H2,
-                                                                  long long ld, int dim, MultiArgs a) {
-  __shared__ double sHre[NT][TM][TK + 1], sHim[NT][TM][TK + 1];
-  __shared__ double sWre[TK][TN + 1], sWim[TK][TN + 1];
+__global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const double2* H1, const double2* H2,
+                                                                      long long ld, int dim, MultiArgs a) {
+  __shared__ double sHre[KS][NT][TM][TK + 1], sHim[KS][NT][TM][TK + 1];
+  __shared__ double sWre[KS][TK][TN + 1], sWim[KS][TK][TN + 1];
   __shared__ double csum[2][2][TN];  // [row half][w|v][state]
   __shared__ int sstop_any;
   const int B = a.B;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wr = wv >> 1, wc = wv & 1;  // wave position in the 2 x 2 arrangement
+  const int kg = wv >> 2;               // K group
+  const int gtid = tid & (kThreads - 1);  // thread within the group
+  const int wq = wv & 3;
+  const int wr = wq >> 1, wc = wq & 1;  // wave position in the 2 x 2 arrangement
 
   // block coordinates: the column blocks of one row block share an XCD
   const int gx = (B + TN - 1) / TN;
@@ -58,39 +71,51 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
     if constexpr (NT == 2) sc[1][tj] = P.a2;
   }
 
-  // staging assignment: H tile TM x TK per term (2 complex per thread),
-  // W tile TK x TN (4 complex per thread)
-  const int h_r = tid >> 3, h_k = (tid & 7) * 2;         // 32 rows x 8 pairs
-  const int w_k = tid >> 4, w_c = (tid & 15) * 4;        // 16 k x 16 quads
+  // staging assignment within the group: H tile TM x TK per term (2 complex
+  // per thread), W tile TK x TN (4 complex per thread)
+  const int h_r = gtid >> 3, h_k = (gtid & 7) * 2;        // 32 rows x 8 pairs
+  const int w_k = gtid >> 4, w_c = (gtid & 15) * 4;       // 16 k x 16 quads
   const d2* W = reinterpret_cast<const d2*>(a.x);
   const d2* Hp[2] = {reinterpret_cast<const d2*>(H1), reinterpret_cast<const d2*>(H2)};
-  d2 hreg[NT][2], wreg[4];
-  auto load_chunk = [&](int k0) {
+  // PD chunks of each group are in flight in registers (slot s holds the
+  // chunks of rounds s, s + PD, ...): two for one term, whose staging
+  // registers leave room for it, one for two terms
+  constexpr int PD = NT == 1 ? 2 : 1;
+  d2 hreg[PD][NT][2], wreg[PD][4];
+  // Loads without branches (every index clamped into the matrix), so the
+  // compiler can count them and wait for one slot while the next is in
+  // flight.  Rows past dim and states past B only reach outputs that are
+  // never stored; entries past dim along K are zeroed on the W side when the
+  // chunk is staged, which also cancels the clamped H columns.
+  auto load_chunk = [&](auto slot, int k0) {
+    constexpr int S = decltype(slot)::value;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int r = row0 + h_r, k = k0 + h_k + u;
-        hreg[t][u] = (r < dim && k < dim) ? __builtin_nontemporal_load(Hp[t] + (long long)r * ld + k) : d2{0.0, 0.0};
+        const int r = min(row0 + h_r, dim - 1), k = min(k0 + h_k + u, dim - 1);
+        hreg[S][t][u] = __builtin_nontemporal_load(Hp[t] + (long long)r * ld + k);
       }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int k = k0 + w_k, c = col0 + w_c + u;
-      wreg[u] = (k < dim && c < B) ? W[(long long)k * B + c] : d2{0.0, 0.0};
+      const int k = min(k0 + w_k, dim - 1), c = min(col0 + w_c + u, B - 1);
+      wreg[S][u] = W[(long long)k * B + c];
     }
   };
-  auto store_chunk = [&]() {
+  auto store_chunk = [&](auto slot, int k0) {
+    constexpr int S = decltype(slot)::value;
+    const bool k_in = k0 + w_k < dim;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        sHre[t][h_r][h_k + u] = hreg[t][u].x;
-        sHim[t][h_r][h_k + u] = hreg[t][u].y;
+        sHre[kg][t][h_r][h_k + u] = hreg[S][t][u].x;
+        sHim[kg][t][h_r][h_k + u] = hreg[S][t][u].y;
       }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      sWre[w_k][w_c + u] = wreg[u].x;
-      sWim[w_k][w_c + u] = wreg[u].y;
+      sWre[kg][w_k][w_c + u] = k_in ? wreg[S][u].x : 0.0;
+      sWim[kg][w_k][w_c + u] = k_in ? wreg[S][u].y : 0.0;
     }
   };
 
@@ -101,25 +126,30 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
     aim[tj] = v4d{0.0, 0.0, 0.0, 0.0};
   }
   const int nk = (dim + TK - 1) / TK;
-  load_chunk(0);
-  for (int kc = 0; kc < nk; ++kc) {
+  const int rounds = (nk + KS - 1) / KS;  // the same barrier count for every group
+  // one round: stage this round's chunk from its slot, refill the slot with
+  // the chunk PD rounds ahead, multiply
+  auto round = [&](auto slot, int it) {
+    const int kc = it * KS + kg;
     __syncthreads();  // previous chunk's operands consumed
-    store_chunk();
+    store_chunk(slot, kc * TK);
     __syncthreads();
-    if (kc + 1 < nk) load_chunk((kc + 1) * TK);  // in flight during the MFMAs
+    // refilled unconditionally (past the end the clamped loads are discarded)
+    load_chunk(slot, (kc + PD * KS) * TK);  // in flight during the MFMAs
+    if (kc >= nk) return;  // this group has no chunk left (uniform per wave)
 #pragma unroll
     for (int ks = 0; ks < TK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
       const int ar = wr * WM + (lane & 15);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const double hre = sHre[t][ar][kk], him = sHim[t][ar][kk];
+        const double hre = sHre[kg][t][ar][kk], him = sHim[kg][t][ar][kk];
         double wre[TJ], wim[TJ];
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj) {
           const int bc = wc * WN + tj * 16 + (lane & 15);
-          wre[tj] = sWre[kk][bc] * sc[t][tj];
-          wim[tj] = sWim[kk][bc] * sc[t][tj];
+          wre[tj] = sWre[kg][kk][bc] * sc[t][tj];
+          wim[tj] = sWim[kg][kk][bc] * sc[t][tj];
         }
         // the 2 TJ accumulators are independent chains: issue one product into each
         // before the second product of any, so dependent MFMAs are never back to back
@@ -135,7 +165,48 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
         }
       }
     }
+  };
+  load_chunk(std::integral_constant<int, 0>{}, kg * TK);
+  if constexpr (PD == 2) {
+    load_chunk(std::integral_constant<int, 1>{}, (KS + kg) * TK);
+    for (int it = 0; it < rounds; it += 2) {
+      round(std::integral_constant<int, 0>{}, it);
+      if (it + 1 < rounds) round(std::integral_constant<int, 1>{}, it + 1);
+    }
+  } else {
+    for (int it = 0; it < rounds; ++it) round(std::integral_constant<int, 0>{}, it);
   }
+
+  // the groups' accumulators, added in group order: group g > 0 parks its
+  // values in the (now idle) W staging buffers, group 0 adds them
+  static_assert(sizeof(sWre) >= sizeof(double) * 4 * TJ * kThreads, "accumulator exchange space");
+  double* xre = &sWre[0][0][0];
+  double* xim = &sWim[0][0][0];
+  __syncthreads();  // every group's last chunk has been read
+#pragma unroll
+  for (int g = 1; g < KS; ++g) {
+    if (kg == g) {
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          xre[(tj * 4 + j) * kThreads + gtid] = are[tj][j];
+          xim[(tj * 4 + j) * kThreads + gtid] = aim[tj][j];
+        }
+    }
+    __syncthreads();
+    if (kg == 0) {
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          are[tj][j] += xre[(tj * 4 + j) * kThreads + gtid];
+          aim[tj][j] += xim[(tj * 4 + j) * kThreads + gtid];
+        }
+    }
+    __syncthreads();
+  }
+  const bool epi = kg == 0;  // group 0 holds the sums; the others only keep the barrier count
 
   // epilogue: accumulator element j of a lane is row lane/16 + 4 j of its
   // 16-row tile, state lane % 16 (the v_mfma_f64_16x16x4f64 output layout)
@@ -145,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
     pw[tj] = 0.0;
     pv[tj] = 0.0;
     const int c = col0 + wc * WN + tj * 16 + (lane & 15);
-    if (c >= B) continue;
+    if (!epi || c >= B) continue;
     const ColParam P = a.prm[c];
     const bool stopped_c = a.check_stop ? load_stopped(&a.slots[c]) != 0 : false;
     const double ys = NT == 2 ? 1.0 : P.a1;
@@ -178,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_leja_kernel(const double2
     pw[tj] += __shfl_xor(pw[tj], 32, 64);
     pv[tj] += __shfl_xor(pv[tj], 16, 64);
     pv[tj] += __shfl_xor(pv[tj], 32, 64);
-    if (lane < 16) {
+    if (epi && lane < 16) {
       csum[wr][0][wc * WN + tj * 16 + lane] = pw[tj];
       csum[wr][1][wc * WN + tj * 16 + lane] = pv[tj];
     }
@@ -218,8 +289,8 @@ hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, l
                              const MultiArgs& a, hipStream_t s) {
   const int gx = (a.B + TN - 1) / TN;
   const int grid = dense_mfma_row_blocks(dim) * gx;
-  if (nterms == 1) dense_mfma_leja_kernel<1><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
-  else dense_mfma_leja_kernel<2><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
+  if (nterms == 1) dense_mfma_leja_kernel<1><<<grid, kMfmaThreads, 0, s>>>(H1, H2, ld, dim, a);
+  else dense_mfma_leja_kernel<2><<<grid, kMfmaThreads, 0, s>>>(H1, H2, ld, dim, a);
   return hipGetLastError();
 }
 

@@ -387,11 +387,14 @@ def test_batched_propagate_per_state_fields():
     c.close()
 
 
-@pytest.mark.parametrize("reserve,per_state", [(True, False), (False, False), (True, True)])
-def test_dense_batched_mfma_matches_oracle(reserve, per_state):
+@pytest.mark.parametrize("reserve,per_state,N", [(True, False, 300), (False, False, 300), (True, True, 300),
+                                                 (True, False, 10), (False, True, 10)])
+def test_dense_batched_mfma_matches_oracle(reserve, per_state, N):
     """Groups of states on dense terms: FP64 MFMA GEMM (assembled exponent when the
-    field is shared and the buffer is reserved, two-term otherwise), ragged dim and batch."""
-    N, Bn, tau, nsteps = 300, 70, 0.005, 6
+    field is shared and the buffer is reserved, two-term otherwise), ragged dim and batch;
+    N = 300 splits 19 K chunks unevenly between the workgroup's two K groups, N = 10
+    leaves the second group without a chunk."""
+    Bn, tau, nsteps = 70, 0.005, 6
     H0 = inputs.powerlaw_hermitian(N, 1.5, seed=31)
     V = inputs.powerlaw_hermitian(N, 1.5, seed=32)
     c = B.Context(max_dim=N, max_batch=Bn)
