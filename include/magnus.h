@@ -59,7 +59,7 @@ extern "C" {
 #define MAGNUS_M2   2   /* Section 2, exponential midpoint rule (order 2): 1 node, 1 exponential */
 #define MAGNUS_CF43 3   /* Section 2, Method Cf4:3: 3 Gauss nodes, 3 exponentials */
 #define MAGNUS_M6   4   /* Section 2, Method M6: 3 Gauss nodes, 1 exponential with nested commutators
-                           (dense terms, after magnus_dense_m6_prepare) */
+                           (after magnus_dense_m6_prepare or magnus_csr_m6_prepare) */
 
 /* Largest interpolation degree per substep the library plans for. */
 #define MAGNUS_MAX_DEGREE 64
@@ -139,8 +139,9 @@ typedef struct {
 
 /* Create a context on `device` owning a workspace for states of up to
  * max_dim entries and batches of up to max_batch states (allocated here; later
- * allocations happen only in magnus_reserve_dense, magnus_dense_commutator and
- * magnus_dense_m6_prepare; about 8 vectors per state).  *out receives the
+ * allocations happen only in magnus_reserve_dense, magnus_dense_commutator,
+ * magnus_dense_m6_prepare, magnus_csr_commutator and magnus_csr_m6_prepare;
+ * about 8 vectors per state).  *out receives the
  * context.  Calls on one context share its workspace: they must not run
  * concurrently from several host threads, and work they enqueue on different
  * streams must not overlap on the device (one stream per context, or the
@@ -200,6 +201,20 @@ int magnus_csr_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream 
  * over the ten (Weyl).  The matrices belong to this pair of terms, as for
  * magnus_dense_commutator.  Synchronous.  Errors as magnus_dense_commutator. */
 int magnus_dense_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
+
+/* Prepare Method M6 (Section 2) on two CSR terms: K = i[H1,H2] as
+ * magnus_csr_commutator forms it, then P_a = -i[H_a,K] (a = 1, 2) by the same
+ * device assembly (at most 1024 products per row of each, else ENOMEM), with
+ * Gershgorin enclosures, kept in the context with seven work vectors of dim
+ * entries.  The nested commutators U_ab = i[H_a,P_b] and R_a = -i[K,P_a] fill
+ * in too quickly to assemble; each Leja iteration of an M6 step applies them
+ * to the iterate as commutators of the assembled matrices (thirteen CSR
+ * products per iteration, with the ten scalars of the dense case), and the
+ * spectral enclosure is the Weyl sum of the assembled matrices' discs and
+ * +-2 rho(A) rho(B) for each nested [A, B].  The matrices belong to this pair
+ * of terms, as for magnus_csr_commutator.  Synchronous.  Errors as
+ * magnus_csr_commutator. */
+int magnus_csr_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream);
 
 /* Free the workspace and the context (NULL is accepted). */
 int magnus_destroy(magnus_ctx* ctx);
@@ -276,7 +291,8 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
  * MAGNUS_M2 (exp(tau A(t_n + tau/2))), MAGNUS_CF43 (Method Cf4:3: three
  * exponentials exp(tau sum_j alpha_ij A_j) on the three Gauss nodes
  * c = 1/2 -+ sqrt(15)/10, 1/2, the factor of the last row acting first),
- * MAGNUS_M6 (dense terms prepared by magnus_dense_m6_prepare; states in turn).
+ * MAGNUS_M6 (terms prepared by magnus_dense_m6_prepare or magnus_csr_m6_prepare;
+ * states in turn).
  *   f_nodes     HOST double[batch_f][nsteps][q]: f(t_n + c_j tau), j < q, with
  *               q = magnus_method_nodes(method) (2, 2, 1, 3, 3).
  *   batch_f     1 (one field for all states) or batch (one field per state).

@@ -67,7 +67,7 @@ EXPORTS = ("magnus_create", "magnus_destroy", "magnus_last_error", "magnus_check
            "magnus_timing", "magnus_timing_read", "magnus_reserve_dense", "magnus_adjoint_workspace_bytes",
            "magnus_propagate_adjoint", "magnus_propagate_ragged", "magnus_method_nodes",
            "magnus_dense_commutator", "magnus_dense_m6_prepare", "magnus_autotune",
-           "magnus_spectral_bounds_lanczos", "magnus_csr_commutator")
+           "magnus_spectral_bounds_lanczos", "magnus_csr_commutator", "magnus_csr_m6_prepare")
 KERNEL_PERSIST, KERNEL_CSR_LEJA3 = 6, 7
 KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA, KERNEL_CSR_MULTI, KERNEL_DENSE_MFMA = 0, 1, 2, 3, 4, 5
 
@@ -104,6 +104,7 @@ def lib():
         "magnus_reserve_dense": (C.c_int, [vp, i64]),
         "magnus_dense_commutator": (C.c_int, [vp, P(Hamiltonian), vp]),
         "magnus_dense_m6_prepare": (C.c_int, [vp, P(Hamiltonian), vp]),
+        "magnus_csr_m6_prepare": (C.c_int, [vp, P(Hamiltonian), vp]),
         "magnus_autotune": (C.c_int, [vp, P(Hamiltonian), i32, P(i32), P(i32), P(dbl), P(dbl), vp]),
         "magnus_spectral_bounds_lanczos": (C.c_int, [vp, P(Hamiltonian), i32, dbl, vp]),
         "magnus_csr_commutator": (C.c_int, [vp, P(Hamiltonian), vp]),
@@ -312,6 +313,12 @@ def magnus_autotune(ctx: Context, ham: DeviceHamiltonian, batch: int = 1) -> dic
 def magnus_dense_m6_prepare(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:
     """Assemble the fixed commutator matrices of M6 for dense terms in the context."""
     _check(lib().magnus_dense_m6_prepare(ctx.handle, C.byref(ham.struct), _stream()))
+    return ham
+
+
+def magnus_csr_m6_prepare(ctx: Context, ham: DeviceHamiltonian) -> DeviceHamiltonian:
+    """Assemble K and P_1, P_2 of M6 for CSR terms in the context (nested commutators matrix-free)."""
+    _check(lib().magnus_csr_m6_prepare(ctx.handle, C.byref(ham.struct), _stream()))
     return ham
 
 

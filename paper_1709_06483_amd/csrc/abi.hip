@@ -92,6 +92,17 @@ struct magnus_ctx {
   double2* kc_val = nullptr;
   int64_t kc_rows = 0, kc_cap = 0, kc_nnz = 0;
   std::tuple<const void*, const void*, const void*, const void*, int64_t> kc_key{nullptr, nullptr, nullptr, nullptr, 0};
+  // magnus_csr_m6_prepare: P_a = -i[H_a, K] (a = 1, 2) as CSR for the pair K
+  // belongs to (valid while pm_key equals kc_key), their enclosures, and seven
+  // work vectors of pm_ws_dim entries for the matrix-free M6 iteration
+  int* pm_rp[2] = {nullptr, nullptr};
+  int* pm_ci[2] = {nullptr, nullptr};
+  double2* pm_val[2] = {nullptr, nullptr};
+  int64_t pm_rows[2] = {0, 0}, pm_cap[2] = {0, 0}, pm_nnz[2] = {0, 0};
+  double pm_lo[2] = {0.0, 0.0}, pm_hi[2] = {0.0, 0.0};
+  double2* pm_ws = nullptr;
+  int64_t pm_ws_dim = 0;
+  std::tuple<const void*, const void*, const void*, const void*, int64_t> pm_key{nullptr, nullptr, nullptr, nullptr, 0};
   // magnus_dense_m6_prepare: the nested commutators of M6, kM6Mats matrices of
   // m6_dim^2 entries, with Gershgorin enclosures, for the pair K belongs to
   double2* m6 = nullptr;
@@ -251,6 +262,7 @@ struct ExpOp {
   const double2* assembled = nullptr;  // dense: the exponent assembled (row stride dim), used with a = 1
   bool has_interval = false;           // spectral enclosure given (else Weyl from a, b, kappa)
   double lo = 0.0, hi = 0.0;
+  const double* m6c = nullptr;         // CSR Method M6: the ten coefficients of the exponent (matrix-free)
 };
 
 // Whether the context holds K = i[H1, H2] of this pair of CSR terms.
@@ -258,6 +270,11 @@ bool csr_comm_ready(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
   return ctx->kc_rp && h->H1.format == MAGNUS_CSR &&
          ctx->kc_key == std::make_tuple((const void*)h->H1.row_ptr, h->H1.val, (const void*)h->H2.row_ptr, h->H2.val,
                                         h->H1.dim);
+}
+
+// Whether the context holds K and P_1, P_2 of Method M6 for this pair of CSR terms.
+bool csr_m6_ready(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  return csr_comm_ready(ctx, h) && ctx->pm_key == ctx->kc_key && ctx->pm_ws && ctx->pm_ws_dim >= h->H1.dim;
 }
 
 // Whether the context holds K = i[H1, H2] of this pair of dense terms.
@@ -317,6 +334,69 @@ hipError_t timed(magnus_ctx* ctx, int kind, hipStream_t s, F f) {
 }
 
 // Launch one Leja iteration (both passes for a commutator exponent).
+// One Leja iteration of Method M6 on CSR terms, the exponent's nested
+// commutators applied to vectors.  With K = i[H1,H2], P_a = -i[H_a,K] assembled
+// and U_ab = i[H_a,P_b], R_a = -i[K,P_a], the Hermitian exponent times w is
+//   y = c0 H1w + c1 H2w + c2 Kw + c3 P1w + c4 P2w
+//     + i H1 (c5 P1w + c6 P2w) - i c5 P1 H1w - i c6 P2 H1w      (c5 U11 + c6 U12)
+//     + i c7 H2 P2w - i c7 P2 H2w                                (c7 U22)
+//     - i K (c8 P1w + c9 P2w) + i c8 P1 Kw + i c9 P2 Kw          (c8 R1 + c9 R2)
+// with H1w, H2w, Kw, P1w, P2w computed once: thirteen CSR products, then the
+// Leja update from y and the stop decision.
+int m6_csr_iteration(magnus_ctx* ctx, const ExpOp& op, double scale, const IterArgs& a, hipStream_t s) {
+  const magnus_hamiltonian* h = op.h;
+  const int dim = (int)h->H1.dim;
+  const double* c = op.m6c;
+  const CsrDev H1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
+  const CsrDev H2{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
+  const CsrDev K{ctx->kc_rp, ctx->kc_ci, ctx->kc_val};
+  const CsrDev P1{ctx->pm_rp[0], ctx->pm_ci[0], ctx->pm_val[0]};
+  const CsrDev P2{ctx->pm_rp[1], ctx->pm_ci[1], ctx->pm_val[1]};
+  double2* v[7];
+  for (int k = 0; k < 7; ++k) v[k] = ctx->pm_ws + (size_t)k * (size_t)ctx->pm_ws_dim;
+  double2 *h1w = v[0], *h2w = v[1], *kw = v[2], *p1w = v[3], *p2w = v[4], *t = v[5], *y = v[6];
+  const double2 one = make_double2(1.0, 0.0);
+  auto im = [](double x) { return make_double2(0.0, x); };
+  const Slot* sl = a.slot;
+  const int cs = a.check_stop;
+  auto mv = [&](const CsrDev& A, const double2* x, double2* out, double2 alpha, bool acc) {
+    return magnus::launch_csr_axpy(A, x, out, alpha, acc, dim, sl, cs, s);
+  };
+  HIP_TRY(mv(H1, a.wcur, h1w, one, false));
+  HIP_TRY(mv(H2, a.wcur, h2w, one, false));
+  HIP_TRY(mv(K, a.wcur, kw, one, false));
+  HIP_TRY(mv(P1, a.wcur, p1w, one, false));
+  HIP_TRY(mv(P2, a.wcur, p2w, one, false));
+  magnus::LinComb L{};
+  L.n = 5;
+  const double2* base[5] = {h1w, h2w, kw, p1w, p2w};
+  for (int k = 0; k < 5; ++k) {
+    L.x[k] = base[k];
+    L.c[k] = c[k];
+  }
+  HIP_TRY(magnus::launch_lincomb(L, y, dim, sl, cs, s));
+  L.n = 2;
+  L.x[0] = p1w;
+  L.x[1] = p2w;
+  L.c[0] = c[5];
+  L.c[1] = c[6];
+  HIP_TRY(magnus::launch_lincomb(L, t, dim, sl, cs, s));
+  HIP_TRY(mv(H1, t, y, im(1.0), true));
+  HIP_TRY(mv(P1, h1w, y, im(-c[5]), true));
+  HIP_TRY(mv(P2, h1w, y, im(-c[6]), true));
+  HIP_TRY(mv(H2, p2w, y, im(c[7]), true));
+  HIP_TRY(mv(P2, h2w, y, im(-c[7]), true));
+  L.c[0] = c[8];
+  L.c[1] = c[9];
+  HIP_TRY(magnus::launch_lincomb(L, t, dim, sl, cs, s));
+  HIP_TRY(mv(K, t, y, im(-1.0), true));
+  HIP_TRY(mv(P1, kw, y, im(c[8]), true));
+  HIP_TRY(mv(P2, kw, y, im(c[9]), true));
+  HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA, s, [&] { return magnus::launch_leja_update(y, scale, dim, a, s); }));
+  HIP_TRY(magnus::launch_leja_decide(a, magnus::leja_update_grid(dim), s));
+  return MAGNUS_OK;
+}
+
 int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, const double2* win,
                      double2* wout, double2* pacc, double tol_sub, int early, hipStream_t s) {
   const magnus_hamiltonian* h = op.h;
@@ -340,6 +420,7 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
   a.wcur = win;
   a.wout = wout;
   a.pacc = pacc;
+  if (op.m6c) return m6_csr_iteration(ctx, op, P.scale, a, s);
   if (h->H1.format == MAGNUS_DENSE) {
     if (op.kappa != 0.0) return fail(MAGNUS_EINVAL, "dense commutator exponents run assembled");
     a.x1 = win;
@@ -560,17 +641,45 @@ int m6_state(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, const dou
                         (tau * tau * b2 * f2 * f2 / 3.0 + tau * b2 * b3 * f2 / 60.0) / 240.0,
                         -tau * tau * b2 * b2 / 14400.0,
                         -tau * tau * b2 * b2 * f2 / 14400.0};
-  const double mlo[10] = {h->H1.lam_min, h->H2.lam_min, h->k_min, ctx->m6_lo[0], ctx->m6_lo[1], ctx->m6_lo[2],
-                          ctx->m6_lo[3], ctx->m6_lo[4], ctx->m6_lo[5], ctx->m6_lo[6]};
-  const double mhi[10] = {h->H1.lam_max, h->H2.lam_max, h->k_max, ctx->m6_hi[0], ctx->m6_hi[1], ctx->m6_hi[2],
-                          ctx->m6_hi[3], ctx->m6_hi[4], ctx->m6_hi[5], ctx->m6_hi[6]};
+  double mlo[10] = {h->H1.lam_min, h->H2.lam_min, h->k_min, ctx->m6_lo[0], ctx->m6_lo[1], ctx->m6_lo[2],
+                    ctx->m6_lo[3], ctx->m6_lo[4], ctx->m6_lo[5], ctx->m6_lo[6]};
+  double mhi[10] = {h->H1.lam_max, h->H2.lam_max, h->k_max, ctx->m6_hi[0], ctx->m6_hi[1], ctx->m6_hi[2],
+                    ctx->m6_hi[3], ctx->m6_hi[4], ctx->m6_hi[5], ctx->m6_hi[6]};
+  if (h->H1.format == MAGNUS_CSR) {
+    // P_a from their Gershgorin discs; the nested commutators i[A, B] are
+    // applied matrix-free, enclosed by +-2 rho(A) rho(B) (rho: the larger end
+    // of an enclosure in absolute value)
+    auto rho = [](double lo_, double hi_) { return std::fmax(std::fabs(lo_), std::fabs(hi_)); };
+    const double rh1 = rho(h->H1.lam_min, h->H1.lam_max), rh2 = rho(h->H2.lam_min, h->H2.lam_max);
+    const double rk = rho(h->k_min, h->k_max);
+    const double rp1 = rho(ctx->pm_lo[0], ctx->pm_hi[0]), rp2 = rho(ctx->pm_lo[1], ctx->pm_hi[1]);
+    const double nested[5] = {2 * rh1 * rp1, 2 * rh1 * rp2, 2 * rh2 * rp2, 2 * rk * rp1, 2 * rk * rp2};
+    mlo[3] = ctx->pm_lo[0];
+    mhi[3] = ctx->pm_hi[0];
+    mlo[4] = ctx->pm_lo[1];
+    mhi[4] = ctx->pm_hi[1];
+    for (int t = 0; t < 5; ++t) {
+      mlo[5 + t] = -nested[t];
+      mhi[5 + t] = nested[t];
+    }
+  }
   // Weyl: the spectrum of a sum of Hermitian matrices lies in the sum of their enclosures
   double lo = 0.0, hi = 0.0;
-  magnus::AssembleTerms T{};
-  T.nterms = 10;
   for (int t = 0; t < 10; ++t) {
     lo += std::fmin(c[t] * mlo[t], c[t] * mhi[t]);
     hi += std::fmax(c[t] * mlo[t], c[t] * mhi[t]);
+  }
+  if (h->H1.format == MAGNUS_CSR) {
+    ExpOp op{h, 0.0, 0.0, 0.0};
+    op.has_interval = true;
+    op.lo = lo;
+    op.hi = hi;
+    op.m6c = c;
+    return run_exponential(ctx, op, tau, in, out, tol_e, o, acc, s);
+  }
+  magnus::AssembleTerms T{};
+  T.nterms = 10;
+  for (int t = 0; t < 10; ++t) {
     T.c[t] = c[t];
     if (t < 2) {
       T.m[t] = reinterpret_cast<const double2*>(t == 0 ? h->H1.val : h->H2.val);
@@ -1084,6 +1193,58 @@ int magnus_dense_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_strea
   return MAGNUS_OK;
 }
 
+// out = i (A B - B A) of two CSR matrices into the storage (rp, ci, val) of
+// rows + 1 and cap entries (grown as needed), with its Gershgorin enclosure.
+int assemble_csr_commutator(magnus_ctx* ctx, const CsrDev& A, const CsrDev& Bm, int64_t dim, int*& rp_d, int*& ci_d,
+                            double2*& val_d, int64_t& rows, int64_t& cap, int64_t& nnz_out, double* lo, double* hi,
+                            hipStream_t s) {
+  // count pass: per-row sizes in a work vector, the overflow flag in the scan buffer
+  int* counts = reinterpret_cast<int*>(ctx->vec(kV));
+  int* overflow = reinterpret_cast<int*>(ctx->scan);
+  HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), s));
+  HIP_TRY(magnus::launch_csr_commutator(false, A, Bm, (int)dim, counts, nullptr, nullptr, nullptr, overflow, s));
+  std::vector<int> cnt((size_t)dim);
+  int ovf = 0;
+  HIP_TRY(hipMemcpyAsync(cnt.data(), counts, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ovf)
+    return fail(MAGNUS_ENOMEM, "a row of A B - B A lists more than %d products (use the matrix-free commutator)",
+                magnus::kCommCap);
+  std::vector<int> rp((size_t)dim + 1, 0);
+  for (int64_t r = 0; r < dim; ++r) {
+    if ((int64_t)rp[r] + cnt[r] > INT32_MAX) return fail(MAGNUS_ENOMEM, "the commutator has more than 2^31 entries");
+    rp[r + 1] = rp[r] + cnt[r];
+  }
+  const int64_t nnz = rp[dim];
+  if (rows < dim || cap < std::max<int64_t>(nnz, 1)) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (rp_d) HIP_TRY(hipFree(rp_d));
+    if (ci_d) HIP_TRY(hipFree(ci_d));
+    if (val_d) HIP_TRY(hipFree(val_d));
+    rp_d = nullptr;
+    ci_d = nullptr;
+    val_d = nullptr;
+    rows = cap = 0;
+    HIP_TRY(hipMalloc(&rp_d, sizeof(int) * (size_t)(dim + 1)));
+    HIP_TRY(hipMalloc(&ci_d, sizeof(int) * (size_t)std::max<int64_t>(nnz, 1)));
+    HIP_TRY(hipMalloc(&val_d, sizeof(double2) * (size_t)std::max<int64_t>(nnz, 1)));
+    rows = dim;
+    cap = std::max<int64_t>(nnz, 1);
+  }
+  HIP_TRY(hipMemcpyAsync(rp_d, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(magnus::launch_csr_commutator(true, A, Bm, (int)dim, counts, rp_d, ci_d, val_d, overflow, s));
+  nnz_out = nnz;
+  magnus_term kt{};
+  kt.format = MAGNUS_CSR;
+  kt.dim = dim;
+  kt.nnz = nnz;
+  kt.row_ptr = rp_d;
+  kt.col_idx = ci_d;
+  kt.val = val_d;
+  return csr_scan(ctx, kt, s, lo, hi);
+}
+
 int magnus_csr_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream) {
   if (!ctx || !h) return fail(MAGNUS_EINVAL, "null argument");
   int rc = check_ham(ctx, h, 0);
@@ -1096,56 +1257,39 @@ int magnus_csr_commutator(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream 
   CsrDev A{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
   CsrDev Bm{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)};
   ctx->kc_key = std::make_tuple(nullptr, nullptr, nullptr, nullptr, (int64_t)0);
-  // count pass: per-row sizes in a work vector, the overflow flag in the scan buffer
-  int* counts = reinterpret_cast<int*>(ctx->vec(kV));
-  int* overflow = reinterpret_cast<int*>(ctx->scan);
-  HIP_TRY(hipMemsetAsync(overflow, 0, sizeof(int), s));
-  HIP_TRY(magnus::launch_csr_commutator(false, A, Bm, (int)dim, counts, nullptr, nullptr, nullptr, overflow, s));
-  std::vector<int> cnt((size_t)dim);
-  int ovf = 0;
-  HIP_TRY(hipMemcpyAsync(cnt.data(), counts, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (ovf)
-    return fail(MAGNUS_ENOMEM, "a row of H1 H2 - H2 H1 lists more than %d products (use the matrix-free commutator)",
-                magnus::kCommCap);
-  std::vector<int> rp((size_t)dim + 1, 0);
-  for (int64_t r = 0; r < dim; ++r) {
-    if ((int64_t)rp[r] + cnt[r] > INT32_MAX) return fail(MAGNUS_ENOMEM, "the commutator has more than 2^31 entries");
-    rp[r + 1] = rp[r] + cnt[r];
-  }
-  const int64_t nnz = rp[dim];
-  if (ctx->kc_rows < dim || ctx->kc_cap < std::max<int64_t>(nnz, 1)) {
-    HIP_TRY(hipStreamSynchronize(s));
-    if (ctx->kc_rp) HIP_TRY(hipFree(ctx->kc_rp));
-    if (ctx->kc_ci) HIP_TRY(hipFree(ctx->kc_ci));
-    if (ctx->kc_val) HIP_TRY(hipFree(ctx->kc_val));
-    ctx->kc_rp = nullptr;
-    ctx->kc_ci = nullptr;
-    ctx->kc_val = nullptr;
-    ctx->kc_rows = ctx->kc_cap = 0;
-    HIP_TRY(hipMalloc(&ctx->kc_rp, sizeof(int) * (size_t)(dim + 1)));
-    HIP_TRY(hipMalloc(&ctx->kc_ci, sizeof(int) * (size_t)std::max<int64_t>(nnz, 1)));
-    HIP_TRY(hipMalloc(&ctx->kc_val, sizeof(double2) * (size_t)std::max<int64_t>(nnz, 1)));
-    ctx->kc_rows = dim;
-    ctx->kc_cap = std::max<int64_t>(nnz, 1);
-  }
-  HIP_TRY(hipMemcpyAsync(ctx->kc_rp, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(magnus::launch_csr_commutator(true, A, Bm, (int)dim, counts, ctx->kc_rp, ctx->kc_ci, ctx->kc_val, overflow,
-                                        s));
-  ctx->kc_nnz = nnz;
-  magnus_term kt{};
-  kt.format = MAGNUS_CSR;
-  kt.dim = dim;
-  kt.nnz = nnz;
-  kt.row_ptr = ctx->kc_rp;
-  kt.col_idx = ctx->kc_ci;
-  kt.val = ctx->kc_val;
   double lo, hi;
-  if ((rc = csr_scan(ctx, kt, s, &lo, &hi))) return rc;
+  if ((rc = assemble_csr_commutator(ctx, A, Bm, dim, ctx->kc_rp, ctx->kc_ci, ctx->kc_val, ctx->kc_rows, ctx->kc_cap,
+                                    ctx->kc_nnz, &lo, &hi, s)))
+    return rc;
   h->k_min = lo;
   h->k_max = hi;
   ctx->kc_key = std::make_tuple((const void*)h->H1.row_ptr, h->H1.val, (const void*)h->H2.row_ptr, h->H2.val, dim);
+  return MAGNUS_OK;
+}
+
+int magnus_csr_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream stream) {
+  int rc = magnus_csr_commutator(ctx, h, stream);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t dim = h->H1.dim;
+  ctx->pm_key = std::make_tuple(nullptr, nullptr, nullptr, nullptr, (int64_t)0);
+  const CsrDev K{ctx->kc_rp, ctx->kc_ci, ctx->kc_val};
+  const CsrDev H[2] = {CsrDev{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)},
+                       CsrDev{h->H2.row_ptr, h->H2.col_idx, reinterpret_cast<const double2*>(h->H2.val)}};
+  for (int a = 0; a < 2; ++a)  // P_a = -i[H_a, K] = i[K, H_a]
+    if ((rc = assemble_csr_commutator(ctx, K, H[a], dim, ctx->pm_rp[a], ctx->pm_ci[a], ctx->pm_val[a],
+                                      ctx->pm_rows[a], ctx->pm_cap[a], ctx->pm_nnz[a], &ctx->pm_lo[a],
+                                      &ctx->pm_hi[a], s)))
+      return rc;
+  if (ctx->pm_ws_dim < dim) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ctx->pm_ws) HIP_TRY(hipFree(ctx->pm_ws));
+    ctx->pm_ws = nullptr;
+    ctx->pm_ws_dim = 0;
+    HIP_TRY(hipMalloc(&ctx->pm_ws, 7 * sizeof(double2) * (size_t)dim));
+    ctx->pm_ws_dim = dim;
+  }
+  ctx->pm_key = ctx->kc_key;
   return MAGNUS_OK;
 }
 
@@ -1312,6 +1456,12 @@ int magnus_destroy(magnus_ctx* ctx) {
   if (ctx->kc_rp) (void)hipFree(ctx->kc_rp);
   if (ctx->kc_ci) (void)hipFree(ctx->kc_ci);
   if (ctx->kc_val) (void)hipFree(ctx->kc_val);
+  for (int a = 0; a < 2; ++a) {
+    if (ctx->pm_rp[a]) (void)hipFree(ctx->pm_rp[a]);
+    if (ctx->pm_ci[a]) (void)hipFree(ctx->pm_ci[a]);
+    if (ctx->pm_val[a]) (void)hipFree(ctx->pm_val[a]);
+  }
+  if (ctx->pm_ws) (void)hipFree(ctx->pm_ws);
   if (ctx->partials) (void)hipFree(ctx->partials);
   if (ctx->scan) (void)hipFree(ctx->scan);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -1584,8 +1734,8 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
     if (!is_fin(f_nodes[k])) return fail(MAGNUS_EDOMAIN, "non-finite field value at node %lld", (long long)k);
   if (method == MAGNUS_M4 && h->H1.format != MAGNUS_CSR && !dense_comm_ready(ctx, h))
     return fail(MAGNUS_EINVAL, "M4 on dense terms needs magnus_dense_commutator for this pair of terms");
-  if (S.sixth && (h->H1.format != MAGNUS_DENSE || !dense_m6_ready(ctx, h)))
-    return fail(MAGNUS_EINVAL, "M6 needs dense terms prepared by magnus_dense_m6_prepare");
+  if (S.sixth && !(h->H1.format == MAGNUS_DENSE ? dense_m6_ready(ctx, h) : csr_m6_ready(ctx, h)))
+    return fail(MAGNUS_EINVAL, "M6 needs terms prepared by magnus_dense_m6_prepare or magnus_csr_m6_prepare");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = begin_call(ctx, s))) return rc;
   if ((rc = ensure_valid(ctx, h, s))) return rc;

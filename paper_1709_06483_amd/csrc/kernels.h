@@ -80,6 +80,23 @@ int csr2_grid(int dim, int rows_per_block);
 // one pass over the matrix to the next; the rest are read non-temporally.
 int csr_keep_entries(int dim);
 
+// Matrix-free M6 on CSR terms: y = alpha A x (+ y when accumulate), 8 lanes
+// per row with a fixed-order sum; a real combination of up to kLinCombMax
+// vectors; the Leja update from y = (Hermitian exponent) w_{i-1} (grid
+// leja_update_grid for the decide kernel).  Each returns at once when
+// check_stop and the slot's substep has stopped.
+constexpr int kLinCombMax = 5;
+struct LinComb {
+  int n;
+  const double2* x[kLinCombMax];
+  double c[kLinCombMax];
+};
+hipError_t launch_csr_axpy(const CsrDev& A, const double2* x, double2* y, double2 alpha, bool accumulate, int dim,
+                           const Slot* slot, int check_stop, hipStream_t s);
+hipError_t launch_lincomb(const LinComb& L, double2* out, int dim, const Slot* slot, int check_stop, hipStream_t s);
+hipError_t launch_leja_update(const double2* y, double scale, int dim, const IterArgs& a, hipStream_t s);
+int leja_update_grid(int dim);
+
 // The streaming kernel (kernels_stream.hip).
 hipError_t launch_csr2_stream(const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a, hipStream_t s);
 int csr2_stream_grid(int dim);

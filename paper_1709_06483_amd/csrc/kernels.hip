@@ -651,6 +651,59 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
 }
 
 // ---------------------------------------------------------------------------
+// Pieces of the matrix-free Method M6 iteration on CSR terms (the exponent's
+// nested commutators applied to vectors as commutators of assembled CSR
+// matrices): y (+)= alpha A x, a real combination of vectors, and the Leja
+// update from a product computed beforehand.
+// ---------------------------------------------------------------------------
+constexpr int kAxpyLanes = 8;  // lanes per row
+
+__global__ __launch_bounds__(kThreads) void csr_axpy_kernel(CsrDev A, const double2* __restrict__ x,
+                                                           double2* __restrict__ y, double2 alpha, int accumulate,
+                                                           int dim, const Slot* slot, int check_stop) {
+  if (check_stop && load_stopped(slot)) return;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  const int r = t / kAxpyLanes, q = t % kAxpyLanes;
+  const d2* xv = reinterpret_cast<const d2*>(x);
+  const d2* av = reinterpret_cast<const d2*>(A.val);
+  d2 acc = {0.0, 0.0};
+  if (r < dim)
+    for (int k = A.rp[r] + q; k < A.rp[r + 1]; k += kAxpyLanes) acc += cmul(av[k], xv[A.ci[k]]);
+  // fixed-order sum over the row's lanes (aligned groups of kAxpyLanes)
+#pragma unroll
+  for (int off = kAxpyLanes / 2; off > 0; off >>= 1) {
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+  }
+  if (r < dim && q == 0) {
+    d2 v = cmul(tod2(alpha), acc);
+    if (accumulate) v += tod2(y[r]);
+    y[r] = fromd2(v);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void lincomb_kernel(LinComb L, double2* __restrict__ out, int dim,
+                                                          const Slot* slot, int check_stop) {
+  if (check_stop && load_stopped(slot)) return;
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  if (r >= dim) return;
+  d2 v = {0.0, 0.0};
+  for (int j = 0; j < L.n; ++j) v += rmul(L.c[j], tod2(L.x[j][r]));
+  out[r] = fromd2(v);
+}
+
+// w_i = scale y - sigma w_{i-1} and the Newton update, y = (the Hermitian
+// exponent) w_{i-1} computed beforehand; one row per thread.
+__global__ __launch_bounds__(kThreads) void leja_update_kernel(const double2* __restrict__ y, double scale, int dim,
+                                                              IterArgs a) {
+  if (a.check_stop && load_stopped(a.slot)) return;
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  double pw = 0.0, pv = 0.0;
+  if (r < dim) leja_row(a, r, rmul(scale, tod2(y[r])), pw, pv);
+  block_partials(a, pw, pv);
+}
+
+// ---------------------------------------------------------------------------
 // Gershgorin discs + structure check (CSR), one thread per row.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void csr_gershgorin_kernel(CsrDev t, int dim, long long nnz,
@@ -837,6 +890,29 @@ hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, lon
   const int keep_rows = (int)std::min<long long>(keep, dim);
   if (H2) dense2_iter_kernel<kDenseRPW2, 2><<<dense2_grid(dim, 2), kThreads, 0, s>>>(H1, H2, dim, ld, a, keep_rows);
   else dense2_iter_kernel<kDenseRPW1, 1><<<dense2_grid(dim, 1), kThreads, 0, s>>>(H1, H1, dim, ld, a, keep_rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_axpy(const CsrDev& A, const double2* x, double2* y, double2 alpha, bool accumulate, int dim,
+                           const Slot* slot, int check_stop, hipStream_t s) {
+  if (dim <= 0) return hipSuccess;
+  const long long threads = (long long)dim * kAxpyLanes;
+  csr_axpy_kernel<<<(unsigned)((threads + kThreads - 1) / kThreads), kThreads, 0, s>>>(A, x, y, alpha, accumulate ? 1 : 0,
+                                                                                      dim, slot, check_stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(const LinComb& L, double2* out, int dim, const Slot* slot, int check_stop, hipStream_t s) {
+  if (dim <= 0) return hipSuccess;
+  if (L.n < 1 || L.n > kLinCombMax) return hipErrorInvalidValue;
+  lincomb_kernel<<<(dim + kThreads - 1) / kThreads, kThreads, 0, s>>>(L, out, dim, slot, check_stop);
+  return hipGetLastError();
+}
+
+int leja_update_grid(int dim) { return (dim + kThreads - 1) / kThreads; }
+
+hipError_t launch_leja_update(const double2* y, double scale, int dim, const IterArgs& a, hipStream_t s) {
+  leja_update_kernel<<<leja_update_grid(dim), kThreads, 0, s>>>(y, scale, dim, a);
   return hipGetLastError();
 }
 

@@ -223,3 +223,57 @@ def test_dense_m6_matches_oracle():
     with pytest.raises(B.MagnusError):
         B.propagate(c, hc, B.M6, tau, nodes("M6", f, tau, 2), dev(inputs.random_states(128, seed=93)))
     c.close()
+
+
+def _random_sparse_hermitian(N, density, seed):
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    A = sp.random(N, N, density=density, random_state=rng, data_rvs=rng.standard_normal).tocsr().astype(complex)
+    A = A + 1j * sp.random(N, N, density=density, random_state=rng, data_rvs=rng.standard_normal).tocsr()
+    A = (A + A.conj().T).tocsr()
+    A.sort_indices()
+    return inputs.CSR.from_scipy(A)
+
+
+@pytest.mark.parametrize("case", ["chain6", "chain8", "random50"])
+def test_csr_m6_matches_oracle(case):
+    """M6 on CSR terms: K and P_a assembled on the device, the nested commutators applied
+    matrix-free in every Leja iteration; 10 steps against the oracle's M6 with exact
+    exponentials.  A second pair of terms is refused until it is prepared in turn."""
+    tau, nsteps = 0.02, 10
+    if case.startswith("chain"):
+        H1, H2 = inputs.chain_terms(int(case[5:]))
+    else:
+        H1, H2 = _random_sparse_hermitian(50, 0.04, 97), _random_sparse_hermitian(50, 0.03, 98)
+    dim = H1.dim
+    c = B.Context(max_dim=dim, max_batch=2)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    f = inputs.cos_field(2.0)
+    fn = nodes("M6", f, tau, nsteps)
+    psi0 = inputs.random_states(dim, seed=95 + dim, batch=2)
+    B.magnus_csr_m6_prepare(c, ham)
+    psi = dev(psi0)
+    _, st = B.propagate(c, ham, B.M6, tau, fn, psi, opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+    out = host(psi)
+    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), f)
+    for k in range(2):
+        assert rel(out[k], mg.propagate("M6", P, tau, nsteps, psi0[k], expm="eig")) <= BUDGET, k
+    assert st["exponentials"] == 2 * nsteps
+    # another pair: refused until prepared
+    other = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H2, H1))
+    with pytest.raises(B.MagnusError) as e:
+        B.propagate(c, other, B.M6, tau, fn[:1], dev(psi0[0]))
+    assert e.value.code == B.EINVAL
+    c.close()
+
+
+def test_csr_m6_prepare_refuses_rows_past_capacity():
+    """Terms whose commutators list more than 1024 products in a row are refused with
+    ENOMEM by the CSR M6 preparation (the caller would use dense terms)."""
+    H1, H2 = _random_sparse_hermitian(60, 0.3, 99), _random_sparse_hermitian(60, 0.3, 100)
+    c = B.Context(max_dim=60, max_batch=1)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    with pytest.raises(B.MagnusError) as e:
+        B.magnus_csr_m6_prepare(c, ham)
+    assert e.value.code == B.ENOMEM
+    c.close()
