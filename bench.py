@@ -56,7 +56,8 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--workload", default="chain_n20",
                     choices=["chain_n20", "chain_n10", "dense_8192", "batched_dense_4096", "ragged_chains",
-                             "adjoint_chain_n16", "adjoint_dense_4096"],
+                             "adjoint_chain_n16", "adjoint_dense_4096", "accuracy_cost_dense",
+                             "accuracy_cost_sparse"],
                     help="chain_n20 is the headline line; the others print one informational line each")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size heuristic for the CSR kernel")
     ap.add_argument("--bounds", choices=["gershgorin", "lanczos"], default="lanczos",
@@ -467,6 +468,60 @@ def other_workload(name: str, args):
         line.update({"metric": f"adjoint loss+gradient time vs forward ({what}, 400 Cf4 steps, 32 params)",
                      "value": ms_g / ms_f, "unit": "ratio", "gradient_ms": ms_g, "forward_ms": ms_f,
                      "loss": loss, "grad_norm": float(np.linalg.norm(grad))})
+    elif name in ("accuracy_cost_dense", "accuracy_cost_sparse"):
+        # Figures 4 and 8 of Section 4 on this GPU: N = 2^12, error at t = 1 against an
+        # M6 reference, each run with the Leja tolerance set to a tenth of the error it
+        # reaches (measured first with a tight tolerance)
+        n, T = 12, 1.0
+        N = 1 << n
+        ctx = B.Context(max_dim=N, max_batch=1)
+        if name == "accuracy_cost_dense":
+            H1, H2 = inputs.heisenberg_nonlocal_terms(n)
+            ctx.reserve_dense(N)
+            ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H1.to_scipy().toarray(),
+                                                                               H2.to_scipy().toarray()))
+            B.magnus_dense_m6_prepare(ctx, ham)
+            what = "Example 1 (non-local Heisenberg, terms stored dense)"
+            paper = {"CF4": 26.9, "M4": 44.0}
+        else:
+            H1, H2 = inputs.heisenberg_local_terms(n)
+            ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+            B.magnus_csr_m6_prepare(ctx, ham)
+            what = "Example 2 (local Heisenberg ring, CSR terms)"
+            paper = {"CF4": 3.09, "M4": 3.81}
+        f = inputs.sin_field(1.0)
+        psi0 = torch.from_numpy(inputs.random_states(N, seed=50)).cuda()
+
+        def run(method, nsteps, budget):
+            tau = T / nsteps
+            fn = np.vectorize(f)(B.magnus_quadrature_nodes(B.METHODS[method], 0.0, tau, nsteps))
+            psi = psi0.clone()
+            ms, (_, st) = _timed(lambda: B.propagate(ctx, ham, B.METHODS[method], tau, fn, psi,
+                                                     opts=B.leja_opts(budget, tol_mode=1), stats=True))
+            return psi, ms, st["iters"]
+
+        ref, ms_ref, _ = run("M6", 4000, 1e-13)
+        rn = float(torch.linalg.norm(ref))
+        sweep = {"M2": [32, 128, 512, 2048, 8192], "M4": [8, 16, 32, 64, 128, 256, 512],
+                 "CF4": [8, 16, 32, 64, 128, 256, 512], "CF43": [8, 16, 32, 64, 128, 256],
+                 "M6": [4, 8, 16, 32, 64]}
+        points = []
+        for m, counts in sweep.items():
+            for k in counts:
+                psi, _, _ = run(m, k, 1e-13)
+                err = float(torch.linalg.norm(psi - ref)) / rn
+                psi, ms, iters = run(m, k, max(err / 10.0, 1e-13))
+                points.append({"method": m, "steps": k, "error": float(torch.linalg.norm(psi - ref)) / rn,
+                               "ms": ms, "leja_iters": iters})
+        targets = [1e-4, 1e-6, 1e-8, 1e-10]
+        best = {f"{t:g}": {m: min([p["ms"] for p in points if p["method"] == m and p["error"] <= t], default=None)
+                           for m in sweep} for t in targets}
+        cf4 = best["1e-10"]["CF4"]
+        line.update({"metric": f"accuracy vs cost, {what}, N=4096, error at t=1 vs an M6 reference "
+                               "(tau=2.5e-4); ms for Cf4 to reach 1e-10",
+                     "value": cf4, "unit": "ms", "higher_is_better": False,
+                     "paper_k80_seconds_to_1e-10": paper, "reference_ms": ms_ref,
+                     "ms_to_reach": best, "points": points})
     print(json.dumps(line), flush=True)
 
 

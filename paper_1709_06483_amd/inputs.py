@@ -110,6 +110,55 @@ def chain_terms(n: int, J: float = 1.0, Delta: float = 0.5, field_axis: str = "x
     return xxz_chain(n, J, Delta), pauli_field(n, field_axis)
 
 
+def heisenberg_nonlocal_terms(n: int):
+    """(H1, H2) of the paper's dense-case model (Section 4, Example 1):
+    H1 = -sum_{i != j} sigma^z_i sigma^z_j / |i - j| (all ordered pairs, so every
+    unordered pair twice; diagonal), H2 = -sum_j sigma^x_j.  The paper stores
+    both densely; their structure is that of a diagonal plus n flips per row."""
+    if n < 2:
+        raise ValueError("the model needs n >= 2 spins")
+    N = 1 << n
+    s = np.arange(N, dtype=np.int64)
+    z = [1 - 2 * ((s >> (n - j)) & 1) for j in range(1, n + 1)]
+    diag = np.zeros(N)
+    for i in range(1, n + 1):
+        for j in range(1, n + 1):
+            if i != j:
+                diag -= z[i - 1] * z[j - 1] / abs(i - j)
+    H1 = _coo_to_csr(s, s, diag.astype(np.complex128), N)
+    x = pauli_field(n, "x").to_scipy()
+    return H1, CSR.from_scipy(-x)
+
+
+def heisenberg_local_terms(n: int, Jx: float = 1.0, Jy: float = 2.0, Jz: float = 3.0):
+    """(H1, H2) of the paper's sparse-case model (Section 4, Example 2):
+    H1 = -1/2 sum_{j=1}^{n} (Jx X_j X_{j+1} + Jy Y_j Y_{j+1} + Jz Z_j Z_{j+1}) with
+    site n + 1 read as site 1 (a ring; the paper leaves the boundary open to
+    reading), H2 = -1/2 sum_j sigma^z_j.  X X + Y Y flips both spins of a bond
+    with amplitude Jx - Jy on an aligned pair and Jx + Jy on an anti-aligned one."""
+    if n < 3:
+        raise ValueError("a ring needs n >= 3 spins")
+    N = 1 << n
+    s = np.arange(N, dtype=np.int64)
+    bits = [((s >> (n - j)) & 1) for j in range(1, n + 1)]
+    diag = np.zeros(N)
+    rows, cols, vals = [s], [s], []
+    for i in range(1, n + 1):
+        k = i % n + 1
+        zi, zk = 1 - 2 * bits[i - 1], 1 - 2 * bits[k - 1]
+        diag += -0.5 * Jz * zi * zk
+        anti = bits[i - 1] != bits[k - 1]
+        amp = np.where(anti, Jx + Jy, Jx - Jy) * -0.5
+        keep = amp != 0.0
+        rows.append(s[keep])
+        cols.append(s[keep] ^ (_site_bit(n, i) | _site_bit(n, k)))
+        vals.append(amp[keep].astype(np.complex128))
+    vals.insert(0, diag.astype(np.complex128))
+    H1 = _coo_to_csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), N)
+    zf = pauli_field(n, "z").to_scipy()
+    return H1, CSR.from_scipy(-0.5 * zf)
+
+
 def powerlaw_hermitian(N: int, alpha: float, seed: int) -> np.ndarray:
     """Dense Hermitian H with H_jk = g_jk / (1 + |j-k|)^alpha, row-major complex128.
 

@@ -277,3 +277,35 @@ def test_csr_m6_prepare_refuses_rows_past_capacity():
         B.magnus_csr_m6_prepare(c, ham)
     assert e.value.code == B.ENOMEM
     c.close()
+
+
+@pytest.mark.parametrize("model", ["nonlocal_dense", "local_csr"])
+def test_paper_example_models_every_method_matches_oracle(model):
+    """The paper's two example models (Section 4) at 6 spins, the non-local one stored
+    dense as in the paper and the local ring as CSR: M2, M4, Cf4, Cf4:3 and M6 over
+    t in [0, 1] in 10 steps of h(t) = sin t each match the oracle with exact exponentials."""
+    n, nsteps = 6, 10
+    tau = 1.0 / nsteps
+    N = 1 << n
+    c = B.Context(max_dim=N, max_batch=1)
+    if model == "nonlocal_dense":
+        H1, H2 = inputs.heisenberg_nonlocal_terms(n)
+        A1, A2 = H1.to_scipy().toarray(), H2.to_scipy().toarray()
+        c.reserve_dense(N)
+        ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(A1, A2))
+        B.magnus_dense_m6_prepare(c, ham)
+    else:
+        H1, H2 = inputs.heisenberg_local_terms(n)
+        A1, A2 = H1.to_scipy(), H2.to_scipy()
+        ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+        B.magnus_csr_m6_prepare(c, ham)
+    f = inputs.sin_field(1.0)
+    psi0 = inputs.random_states(N, seed=51)
+    P = mg.two_term(A1, A2, f)
+    for method in ("M2", "M4", "CF4", "CF43", "M6"):
+        psi = dev(psi0)
+        B.propagate(c, ham, B.METHODS[method], tau, nodes(method, f, tau, nsteps), psi,
+                    opts=B.leja_opts(BUDGET, tol_mode=1))
+        ref = mg.propagate(method, P, tau, nsteps, psi0, expm="eig")
+        assert rel(host(psi), ref) <= BUDGET, method
+    c.close()

@@ -70,3 +70,34 @@ def test_fourier_field():
     t = 0.37
     assert abs(f(t) - sum(th[k] * np.sin((k + 1) * np.pi * t / 2.0) for k in range(3))) < 1e-15
     assert np.allclose(inputs.fourier_basis(3, 2.0)(t), [np.sin((k + 1) * np.pi * t / 2.0) for k in range(3)])
+
+
+def _kron_site(n, j, P):
+    """sigma^P on site j (1-based, site 1 = the leftmost factor) of n spins, dense."""
+    I2 = np.eye(2)
+    out = np.array([[1.0 + 0j]])
+    for k in range(1, n + 1):
+        out = np.kron(out, P if k == j else I2)
+    return out
+
+
+def test_paper_heisenberg_models_match_kronecker_products():
+    """The paper's two example models (Section 4) built from explicit tensor products of
+    the Pauli matrices, for a few small n, equal the generators' CSR terms."""
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    Y = np.array([[0, -1j], [1j, 0]], dtype=complex)
+    Z = np.array([[1, 0], [0, -1]], dtype=complex)
+    for n in (3, 4, 5):
+        H1, H2 = inputs.heisenberg_nonlocal_terms(n)
+        ref1 = sum(-(1.0 / abs(i - j)) * _kron_site(n, i, Z) @ _kron_site(n, j, Z)
+                   for i in range(1, n + 1) for j in range(1, n + 1) if i != j)
+        ref2 = sum(-_kron_site(n, j, X) for j in range(1, n + 1))
+        assert np.allclose(H1.to_scipy().toarray(), ref1, atol=1e-13)
+        assert np.allclose(H2.to_scipy().toarray(), ref2, atol=1e-13)
+        H1, H2 = inputs.heisenberg_local_terms(n)
+        ref1 = sum(-0.5 * (1.0 * _kron_site(n, j, X) @ _kron_site(n, j % n + 1, X)
+                           + 2.0 * _kron_site(n, j, Y) @ _kron_site(n, j % n + 1, Y)
+                           + 3.0 * _kron_site(n, j, Z) @ _kron_site(n, j % n + 1, Z)) for j in range(1, n + 1))
+        ref2 = sum(-0.5 * _kron_site(n, j, Z) for j in range(1, n + 1))
+        assert np.allclose(H1.to_scipy().toarray(), ref1, atol=1e-13)
+        assert np.allclose(H2.to_scipy().toarray(), ref2, atol=1e-13)
