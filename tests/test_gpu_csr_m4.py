@@ -44,8 +44,12 @@ def _random_sparse_hermitian(N, density, seed):
     return inputs.CSR.from_scipy(H), H.toarray()
 
 
+@pytest.mark.parametrize("variant", ["0", "7"])
 @pytest.mark.parametrize("kind", ["chain", "random"])
-def test_assembled_commutator_m4_matches_oracle_and_matrix_free(kind):
+def test_assembled_commutator_m4_matches_oracle_and_matrix_free(kind, variant, monkeypatch):
+    """variant "0" is the size rule at these sizes; "7" forces the streamed two-term
+    tiles, under which the three-term pass takes the 8-row wave tiles."""
+    monkeypatch.setenv("MAGNUS_CSR_VARIANT", variant)
     if kind == "chain":
         H1, H2 = inputs.chain_terms(10)
         A1, A2 = H1.to_scipy().toarray(), H2.to_scipy().toarray()
