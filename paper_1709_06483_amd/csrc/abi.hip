@@ -307,10 +307,6 @@ int rows_per_block(magnus_ctx* ctx, const magnus_hamiltonian* h) {
   return variant_rows(it == ctx->tuned_variant.end() ? 0 : it->second, h->H1.dim);
 }
 
-// The two passes of the matrix-free commutator have no streaming variant:
-// they run the 8-row wave tiles when the plain iteration streams.
-int comm_rows(int rpb) { return rpb == magnus::kStreamTile ? magnus::kWaveTile + 8 : rpb; }
-
 hipEvent_t next_event(magnus_ctx* ctx) {
   if (ctx->pool_used == ctx->pool.size()) {
     hipEvent_t e;
@@ -454,22 +450,40 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
     HIP_TRY(magnus::launch_leja_decide(a, magnus::csr3_grid(dim), s));
     return MAGNUS_OK;
   }
-  // commutator: pass 1 writes U = H1 w, V = H2 w; pass 2 applies H1 V and H2 U
-  const int crpb = comm_rows(rpb);
   double2* U = ctx->vec(kU);
   double2* V = ctx->vec(kV);
+  if (rpb == magnus::kStreamTile) {
+    // streamed commutator: pass 1 writes U = a1 w + i k H2 w and V = a2 w - i k H1 w,
+    // pass 2 is the two-term iteration on H1 U + H2 V
+    IterArgs p1 = a;
+    p1.x1 = win;
+    p1.x2 = win;
+    p1.wout = U;
+    p1.pacc = V;
+    HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_SPLIT, s,
+                  [&] { return magnus::launch_csr2_iter(magnus::kSplitComm, t1, t2, dim, p1, rpb, s); }));
+    a.x1 = U;
+    a.x2 = V;
+    a.a1 = 1.0;
+    a.a2 = 1.0;
+    HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_COMM, s,
+                  [&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }));
+    HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
+    return MAGNUS_OK;
+  }
+  // commutator: pass 1 writes U = H1 w, V = H2 w; pass 2 applies H1 V and H2 U
   IterArgs p1 = a;
   p1.x1 = win;
   p1.x2 = win;
   p1.wout = U;
   p1.pacc = V;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_SPLIT, s,
-                [&] { return magnus::launch_csr2_iter(magnus::kSplit, t1, t2, dim, p1, crpb, s); }));
+                [&] { return magnus::launch_csr2_iter(magnus::kSplit, t1, t2, dim, p1, rpb, s); }));
   a.x1 = V;
   a.x2 = U;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_COMM, s,
-                [&] { return magnus::launch_csr2_iter(magnus::kLejaComm, t1, t2, dim, a, crpb, s); }));
-  HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, crpb), s));
+                [&] { return magnus::launch_csr2_iter(magnus::kLejaComm, t1, t2, dim, a, rpb, s); }));
+  HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
   return MAGNUS_OK;
 }
 

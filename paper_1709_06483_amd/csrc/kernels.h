@@ -31,6 +31,8 @@ enum IterMode : int {
   kLeja = 0,       // y = a1 H1 x1 + a2 H2 x2, then the Leja update
   kSplit = 1,      // out1 = H1 x1, out2 = H2 x2 (first half of a commutator pass)
   kLejaComm = 2,   // y = a1 x2 + a2 x1 + i k (H1 x1 - H2 x2), then the Leja update
+  kSplitComm = 3,  // out1 = a1 x + i k H2 x, out2 = a2 x - i k H1 x with x = x1 = x2 = wcur
+                   // (streamed kernel only; kLeja over out1, out2 with a1 = a2 = 1 completes it)
 };
 
 // One Leja iteration: w_i = X w_{i-1} - xi_{i-1} w_{i-1}, p += d_i w_i, where
@@ -63,7 +65,7 @@ constexpr int kRowLane = -64;
 // kWaveTile + R selects the wave-tile kernel with R rows per wave (R = 8, 16;
 // four waves per workgroup).
 constexpr int kWaveTile = 1000;
-// kStreamTile selects the streaming wave-tile kernel (mode kLeja only): every
+// kStreamTile selects the streaming wave-tile kernel (modes kLeja and kSplitComm): every
 // wave walks 8 tiles of 8 rows, copying each tile's entries into LDS one tile
 // ahead.
 constexpr int kStreamTile = 2000;
@@ -98,7 +100,8 @@ hipError_t launch_leja_update(const double2* y, double scale, int dim, const Ite
 int leja_update_grid(int dim);
 
 // The streaming kernel (kernels_stream.hip).
-hipError_t launch_csr2_stream(const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a, hipStream_t s);
+hipError_t launch_csr2_stream(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a,
+                              hipStream_t s);
 int csr2_stream_grid(int dim);
 
 // Gershgorin enclosure and structural check of one CSR term.  Writes per

@@ -815,10 +815,8 @@ int csr2_grid(int dim, int rows_per_block) {
 
 hipError_t launch_csr2_iter(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a,
                             int rows_per_block, hipStream_t s) {
-  if (rows_per_block == kStreamTile) {
-    if (mode != kLeja) return hipErrorInvalidValue;
-    return launch_csr2_stream(t1, t2, dim, a, s);
-  }
+  if (rows_per_block == kStreamTile) return launch_csr2_stream(mode, t1, t2, dim, a, s);
+  if (mode == kSplitComm) return hipErrorInvalidValue;
   const int grid = csr2_grid(dim, rows_per_block);
 #define MAGNUS_CSR_CASE(R, M) \
   if (rows_per_block == R && mode == M) { csr2_iter_kernel<R, M><<<grid, kThreads, 0, s>>>(t1, t2, dim, a); return hipGetLastError(); }

@@ -1,5 +1,6 @@
 // Two-term CSR Leja iteration (Section 3's recurrence on a1 H1 + a2 H2), the
-// streaming wave-tile variant.
+// streaming wave-tile variant; and the first of the two passes of a Method M4
+// iteration with the commutator applied matrix-free.
 //
 // Every wave walks 8 tiles of 8 consecutive rows.  A tile's column indices and
 // values (term 1's entries of its rows, then term 2's) travel from HBM
@@ -109,8 +110,15 @@ struct Tile {
 // once when the wave starts and stored once when it ends, and no store is
 // outstanding inside the tile loop (a pending store would make every wait on
 // a gather wait for all outstanding loads, the next chunk's copy included).
+//
+// MODE kLeja: y = a1 H1 x1 + a2 H2 x2, then the Leja update and norm partials.
+// MODE kSplitComm (x1 = x2 = wcur = w): wout = a1 w + i k H2 w and
+// pacc = a2 w - i k H1 w, so that the kLeja pass H1 wout + H2 pacc (a1 = a2 = 1)
+// is a1 H1 w + a2 H2 w + k i[H1, H2] w.
+template <int MODE>
 __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a,
                                                                   int keep_entries) {
+  static_assert(MODE == kLeja || MODE == kSplitComm, "streamed modes");
   __shared__ StreamLds sh;
   // the stop flag is the same for every wave; it is tested once the first
   // row pointers are in flight
@@ -180,7 +188,7 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
   const int my_ld = my_valid ? my_row : 0;
   const d2 w_old = tod2(a.wcur[my_ld]);
   d2 p_old = {0.0, 0.0};
-  if (!a.first) p_old = tod2(a.pacc[my_ld]);
+  if (MODE == kLeja && !a.first) p_old = tod2(a.pacc[my_ld]);
   if (stopped) return;  // uniform over the workgroup
 
   Tile T = tile_of(0, rp_cur);
@@ -284,7 +292,11 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
       acc2.y += __shfl_xor(acc2.y, off, 64);
     }
     // the lanes of slot j hold this tile's rows: the Leja update
-    if (g == j && r < T.nr) {
+    if (MODE == kSplitComm && g == j && r < T.nr) {
+      res_w = rmul(a.a1, w_old) + rmul(a.kap, d2{-acc2.y, acc2.x});
+      res_p = rmul(a.a2, w_old) - rmul(a.kap, d2{-acc1.y, acc1.x});
+    }
+    if (MODE == kLeja && g == j && r < T.nr) {
       const d2 y = rmul(a.a1, acc1) + rmul(a.a2, acc2);
       const d2 wn = y - rmul(a.sigma, w_old);
       if (a.first) {
@@ -305,6 +317,7 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
     a.pacc[my_row] = fromd2(res_p);
   }
   wait_vmem();  // no copy into this wave's buffers is still in flight
+  if (MODE != kLeja) return;
   pw = wave_sum(pw);
   pv = wave_sum(pv);
   double* red = reinterpret_cast<double*>(&sh.val[wv][0][0]);  // this wave's own buffer
@@ -332,11 +345,19 @@ int csr2_stream_grid(int dim) {
   return (int)std::max<long long>(1, (dim + rows - 1) / rows);
 }
 
-hipError_t launch_csr2_stream(const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a, hipStream_t s) {
+hipError_t launch_csr2_stream(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a,
+                              hipStream_t s) {
   // entries (20 bytes each, both terms) kept resident in the MALL
   const long long keep = std::max(0LL, kMallKeepBytes - 80LL * dim) / 20;
   const int keep_entries = (int)std::min<long long>(keep, 1LL << 30);
-  csr2_stream_kernel<<<csr2_stream_grid(dim), kThreads, 0, s>>>(t1, t2, dim, a, keep_entries);
+  if (mode == kLeja) {
+    csr2_stream_kernel<kLeja><<<csr2_stream_grid(dim), kThreads, 0, s>>>(t1, t2, dim, a, keep_entries);
+  } else if (mode == kSplitComm) {
+    if (a.x1 != a.wcur || a.x2 != a.wcur) return hipErrorInvalidValue;  // w is read as its own rows
+    csr2_stream_kernel<kSplitComm><<<csr2_stream_grid(dim), kThreads, 0, s>>>(t1, t2, dim, a, keep_entries);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

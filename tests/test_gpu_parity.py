@@ -680,7 +680,8 @@ def test_small_state_path_selection(n, batch, persistent, monkeypatch):
 def test_streamed_tiles_small_and_degenerate(N, variant, monkeypatch):
     """The streamed wave-tile kernel on dimensions that leave most tiles and waves of a
     workgroup empty, rows without entries and an H2 without entries (null arrays):
-    it matches the oracle and the 8-row wave-tile kernel, which sums in the same order."""
+    it matches the oracle and the 8-row wave-tile kernel, which sums in the same order;
+    and its two-pass form of the matrix-free commutator matches the oracle."""
     import scipy.sparse as sp
     H1, A1 = _tiny_hermitian(N, seed=1900 + N, density=0.5 if N <= 130 else 0.02,
                              empty_rows=(N // 2,) if N > 2 else ())
@@ -699,3 +700,11 @@ def test_streamed_tiles_small_and_degenerate(N, variant, monkeypatch):
         ref = oe.expmv_taylor(oracle_exponent(sp.csr_matrix(A1), sp.csr_matrix(A2d), 0.7, -0.3, 0.0, 0.05), v)
         assert rel(out[variant], ref) <= 20 * tol, N
         assert rel(out[variant], out["5"]) <= 1e-14, N
+    # a commutator exponent: the matrix-free commutator's two streamed passes
+    monkeypatch.setenv("MAGNUS_CSR_VARIANT", variant)
+    c = B.Context(max_dim=N)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    w = host(B.expmv_leja(c, ham, 0.7, -0.3, 0.02, 0.05, dev(v), opts=B.leja_opts(tol)))
+    c.close()
+    ref = oe.expmv_taylor(oracle_exponent(sp.csr_matrix(A1), sp.csr_matrix(A2), 0.7, -0.3, 0.02, 0.05), v)
+    assert rel(w, ref) <= 20 * tol, N
