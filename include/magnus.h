@@ -205,11 +205,12 @@ int magnus_dense_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_strea
 /* Prepare Method M6 (Section 2) on two CSR terms: K = i[H1,H2] as
  * magnus_csr_commutator forms it, then P_a = -i[H_a,K] (a = 1, 2) by the same
  * device assembly (at most 1024 products per row of each, else ENOMEM), with
- * Gershgorin enclosures, kept in the context with seven work vectors of dim
+ * Gershgorin enclosures, kept in the context with six work vectors of dim
  * entries.  The nested commutators U_ab = i[H_a,P_b] and R_a = -i[K,P_a] fill
  * in too quickly to assemble; each Leja iteration of an M6 step applies them
- * to the iterate as commutators of the assembled matrices (thirteen CSR
- * products per iteration, with the ten scalars of the dense case), and the
+ * to the iterate as commutators of the assembled matrices (with the ten
+ * scalars of the dense case, the products grouped by matrix: two passes over
+ * H1, H2, K, P1 and P2 per iteration), and the
  * spectral enclosure is the Weyl sum of the assembled matrices' discs and
  * +-2 rho(A) rho(B) for each nested [A, B].  The matrices belong to this pair
  * of terms, as for magnus_csr_commutator.  Synchronous.  Errors as

@@ -93,8 +93,8 @@ struct magnus_ctx {
   int64_t kc_rows = 0, kc_cap = 0, kc_nnz = 0;
   std::tuple<const void*, const void*, const void*, const void*, int64_t> kc_key{nullptr, nullptr, nullptr, nullptr, 0};
   // magnus_csr_m6_prepare: P_a = -i[H_a, K] (a = 1, 2) as CSR for the pair K
-  // belongs to (valid while pm_key equals kc_key), their enclosures, and seven
-  // work vectors of pm_ws_dim entries for the matrix-free M6 iteration
+  // belongs to (valid while pm_key equals kc_key), their enclosures, and six
+  // work vectors of pm_ws_dim entries for the M6 iteration (u_1..u_5, y0)
   int* pm_rp[2] = {nullptr, nullptr};
   int* pm_ci[2] = {nullptr, nullptr};
   double2* pm_val[2] = {nullptr, nullptr};
@@ -337,8 +337,12 @@ hipError_t timed(magnus_ctx* ctx, int kind, hipStream_t s, F f) {
 //     + i H1 (c5 P1w + c6 P2w) - i c5 P1 H1w - i c6 P2 H1w      (c5 U11 + c6 U12)
 //     + i c7 H2 P2w - i c7 P2 H2w                                (c7 U22)
 //     - i K (c8 P1w + c9 P2w) + i c8 P1 Kw + i c9 P2 Kw          (c8 R1 + c9 R2)
-// with H1w, H2w, Kw, P1w, P2w computed once: thirteen CSR products, then the
-// Leja update from y and the stop decision.
+// Grouped by matrix, y = y0 + H1 u1 + H2 u2 + K u3 + P1 u4 + P2 u5 with
+// y0 the first line and u1 = i(c5 P1w + c6 P2w), u2 = i c7 P2w,
+// u3 = -i(c8 P1w + c9 P2w), u4 = i(c8 Kw - c5 H1w), u5 = i(c9 Kw - c6 H1w - c7 H2w):
+// one pass over the five matrices forms y0 and the u's row by row, a second
+// applies them and makes the Leja update, then the stop decision (ten matrix
+// reads where the thirteen products one by one would make thirteen).
 int m6_csr_iteration(magnus_ctx* ctx, const ExpOp& op, double scale, const IterArgs& a, hipStream_t s) {
   const magnus_hamiltonian* h = op.h;
   const int dim = (int)h->H1.dim;
@@ -348,48 +352,15 @@ int m6_csr_iteration(magnus_ctx* ctx, const ExpOp& op, double scale, const IterA
   const CsrDev K{ctx->kc_rp, ctx->kc_ci, ctx->kc_val};
   const CsrDev P1{ctx->pm_rp[0], ctx->pm_ci[0], ctx->pm_val[0]};
   const CsrDev P2{ctx->pm_rp[1], ctx->pm_ci[1], ctx->pm_val[1]};
-  double2* v[7];
-  for (int k = 0; k < 7; ++k) v[k] = ctx->pm_ws + (size_t)k * (size_t)ctx->pm_ws_dim;
-  double2 *h1w = v[0], *h2w = v[1], *kw = v[2], *p1w = v[3], *p2w = v[4], *t = v[5], *y = v[6];
-  const double2 one = make_double2(1.0, 0.0);
-  auto im = [](double x) { return make_double2(0.0, x); };
-  const Slot* sl = a.slot;
-  const int cs = a.check_stop;
-  auto mv = [&](const CsrDev& A, const double2* x, double2* out, double2 alpha, bool acc) {
-    return magnus::launch_csr_axpy(A, x, out, alpha, acc, dim, sl, cs, s);
-  };
-  HIP_TRY(mv(H1, a.wcur, h1w, one, false));
-  HIP_TRY(mv(H2, a.wcur, h2w, one, false));
-  HIP_TRY(mv(K, a.wcur, kw, one, false));
-  HIP_TRY(mv(P1, a.wcur, p1w, one, false));
-  HIP_TRY(mv(P2, a.wcur, p2w, one, false));
-  magnus::LinComb L{};
-  L.n = 5;
-  const double2* base[5] = {h1w, h2w, kw, p1w, p2w};
-  for (int k = 0; k < 5; ++k) {
-    L.x[k] = base[k];
-    L.c[k] = c[k];
-  }
-  HIP_TRY(magnus::launch_lincomb(L, y, dim, sl, cs, s));
-  L.n = 2;
-  L.x[0] = p1w;
-  L.x[1] = p2w;
-  L.c[0] = c[5];
-  L.c[1] = c[6];
-  HIP_TRY(magnus::launch_lincomb(L, t, dim, sl, cs, s));
-  HIP_TRY(mv(H1, t, y, im(1.0), true));
-  HIP_TRY(mv(P1, h1w, y, im(-c[5]), true));
-  HIP_TRY(mv(P2, h1w, y, im(-c[6]), true));
-  HIP_TRY(mv(H2, p2w, y, im(c[7]), true));
-  HIP_TRY(mv(P2, h2w, y, im(-c[7]), true));
-  L.c[0] = c[8];
-  L.c[1] = c[9];
-  HIP_TRY(magnus::launch_lincomb(L, t, dim, sl, cs, s));
-  HIP_TRY(mv(K, t, y, im(-1.0), true));
-  HIP_TRY(mv(P1, kw, y, im(c[8]), true));
-  HIP_TRY(mv(P2, kw, y, im(c[9]), true));
-  HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA, s, [&] { return magnus::launch_leja_update(y, scale, dim, a, s); }));
-  HIP_TRY(magnus::launch_leja_decide(a, magnus::leja_update_grid(dim), s));
+  magnus::M6Terms T{{H1, H2, K, P1, P2}};
+  magnus::M6Coef C{};
+  for (int k = 0; k < 10; ++k) C.c[k] = c[k];
+  magnus::M6Vecs V{};
+  for (int k = 0; k < magnus::kM6Terms; ++k) V.u[k] = ctx->pm_ws + (size_t)k * (size_t)ctx->pm_ws_dim;
+  V.y0 = ctx->pm_ws + (size_t)magnus::kM6Terms * (size_t)ctx->pm_ws_dim;
+  HIP_TRY(magnus::launch_m6_stage_a(T, a.wcur, C, V, dim, a.slot, a.check_stop, s));
+  HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA, s, [&] { return magnus::launch_m6_stage_b(T, V, scale, dim, a, s); }));
+  HIP_TRY(magnus::launch_leja_decide(a, magnus::m6_grid(dim), s));
   return MAGNUS_OK;
 }
 
@@ -1300,7 +1271,7 @@ int magnus_csr_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_stream 
     if (ctx->pm_ws) HIP_TRY(hipFree(ctx->pm_ws));
     ctx->pm_ws = nullptr;
     ctx->pm_ws_dim = 0;
-    HIP_TRY(hipMalloc(&ctx->pm_ws, 7 * sizeof(double2) * (size_t)dim));
+    HIP_TRY(hipMalloc(&ctx->pm_ws, (magnus::kM6Terms + 1) * sizeof(double2) * (size_t)dim));
     ctx->pm_ws_dim = dim;
   }
   ctx->pm_key = ctx->kc_key;

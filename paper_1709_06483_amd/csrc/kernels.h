@@ -82,22 +82,30 @@ int csr2_grid(int dim, int rows_per_block);
 // one pass over the matrix to the next; the rest are read non-temporally.
 int csr_keep_entries(int dim);
 
-// Matrix-free M6 on CSR terms: y = alpha A x (+ y when accumulate), 8 lanes
-// per row with a fixed-order sum; a real combination of up to kLinCombMax
-// vectors; the Leja update from y = (Hermitian exponent) w_{i-1} (grid
-// leja_update_grid for the decide kernel).  Each returns at once when
-// check_stop and the slot's substep has stopped.
-constexpr int kLinCombMax = 5;
-struct LinComb {
-  int n;
-  const double2* x[kLinCombMax];
-  double c[kLinCombMax];
+// Method M6 on CSR terms, one Leja iteration in two passes over the five
+// matrices (H1, H2, K, P1, P2).  Stage A: with s_k = M_k w,
+//   y0 = sum_k c_k s_k, u1 = i(c5 s3 + c6 s4), u2 = i c7 s4,
+//   u3 = -i(c8 s3 + c9 s4), u4 = i(c8 s2 - c5 s0), u5 = i(c9 s2 - c6 s0 - c7 s1);
+// stage B: y = y0 + sum_k M_k u_{k+1}, then the Leja update from y (the
+// Hermitian exponent times w_{i-1}) with its norm partials (grid m6_grid for
+// the decide kernel).  Both return at once when check_stop and the slot's
+// substep has stopped.
+constexpr int kM6Terms = 5;
+struct M6Terms {
+  CsrDev m[kM6Terms];
 };
-hipError_t launch_csr_axpy(const CsrDev& A, const double2* x, double2* y, double2 alpha, bool accumulate, int dim,
-                           const Slot* slot, int check_stop, hipStream_t s);
-hipError_t launch_lincomb(const LinComb& L, double2* out, int dim, const Slot* slot, int check_stop, hipStream_t s);
-hipError_t launch_leja_update(const double2* y, double scale, int dim, const IterArgs& a, hipStream_t s);
-int leja_update_grid(int dim);
+struct M6Coef {
+  double c[10];
+};
+struct M6Vecs {
+  double2* u[kM6Terms];  // stage B's input vectors, in the order of M6Terms
+  double2* y0;
+};
+hipError_t launch_m6_stage_a(const M6Terms& T, const double2* w, const M6Coef& C, const M6Vecs& V, int dim,
+                             const Slot* slot, int check_stop, hipStream_t s);
+hipError_t launch_m6_stage_b(const M6Terms& T, const M6Vecs& V, double scale, int dim, const IterArgs& a,
+                             hipStream_t s);
+int m6_grid(int dim);
 
 // The streaming kernel (kernels_stream.hip).
 hipError_t launch_csr2_stream(int mode, const CsrDev& t1, const CsrDev& t2, int dim, const IterArgs& a,

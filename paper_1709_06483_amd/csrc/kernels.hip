@@ -651,55 +651,78 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
 }
 
 // ---------------------------------------------------------------------------
-// Pieces of the matrix-free Method M6 iteration on CSR terms (the exponent's
-// nested commutators applied to vectors as commutators of assembled CSR
-// matrices): y (+)= alpha A x, a real combination of vectors, and the Leja
-// update from a product computed beforehand.
+// The Method M6 iteration on CSR terms (the exponent's nested commutators
+// applied to vectors as commutators of assembled CSR matrices), in two
+// passes over the five matrices M = (H1, H2, K, P1, P2), 8 lanes per row,
+// each term's products summed in a fixed order:
+//   stage A: s_k = (M_k w)[r] for the row, then on the row itself y0 and the
+//            five vectors u_k that stage B multiplies (see M6Vecs);
+//   stage B: y = y0 + sum_k M_k u_k, then the Leja update and norm partials.
+// Grouping the products by matrix reads P1 and P2 twice per iteration where
+// applying each commutator product separately reads them three and four times.
 // ---------------------------------------------------------------------------
-constexpr int kAxpyLanes = 8;  // lanes per row
+constexpr int kM6Lanes = 8;  // lanes per row
 
-__global__ __launch_bounds__(kThreads) void csr_axpy_kernel(CsrDev A, const double2* __restrict__ x,
-                                                           double2* __restrict__ y, double2 alpha, int accumulate,
-                                                           int dim, const Slot* slot, int check_stop) {
+__device__ __forceinline__ d2 times_i(d2 v) { return d2{-v.y, v.x}; }
+
+__global__ __launch_bounds__(kThreads) void m6_stage_a_kernel(M6Terms T, const double2* __restrict__ w, M6Coef C,
+                                                             M6Vecs V, int dim, const Slot* slot, int check_stop) {
   if (check_stop && load_stopped(slot)) return;
-  const int t = blockIdx.x * kThreads + threadIdx.x;
-  const int r = t / kAxpyLanes, q = t % kAxpyLanes;
-  const d2* xv = reinterpret_cast<const d2*>(x);
-  const d2* av = reinterpret_cast<const d2*>(A.val);
-  d2 acc = {0.0, 0.0};
-  if (r < dim)
-    for (int k = A.rp[r] + q; k < A.rp[r + 1]; k += kAxpyLanes) acc += cmul(av[k], xv[A.ci[k]]);
-  // fixed-order sum over the row's lanes (aligned groups of kAxpyLanes)
+  const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const int r = (int)(t / kM6Lanes), q = (int)(t % kM6Lanes);
+  const d2* wv = reinterpret_cast<const d2*>(w);
+  d2 sk[kM6Terms];
 #pragma unroll
-  for (int off = kAxpyLanes / 2; off > 0; off >>= 1) {
+  for (int k = 0; k < kM6Terms; ++k) {
+    d2 acc = {0.0, 0.0};
+    if (r < dim) {
+      const d2* av = reinterpret_cast<const d2*>(T.m[k].val);
+      for (int e = T.m[k].rp[r] + q; e < T.m[k].rp[r + 1]; e += kM6Lanes) acc += cmul(av[e], wv[T.m[k].ci[e]]);
+    }
+#pragma unroll
+    for (int off = kM6Lanes / 2; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    sk[k] = acc;
+  }
+  if (r >= dim) return;
+  const double* c = C.c;
+  // lane q of the row writes output q (all lanes hold the five sums)
+  d2 out;
+  switch (q) {
+    case 0: out = rmul(c[0], sk[0]) + rmul(c[1], sk[1]) + rmul(c[2], sk[2]) + rmul(c[3], sk[3]) + rmul(c[4], sk[4]); break;
+    case 1: out = times_i(rmul(c[5], sk[3]) + rmul(c[6], sk[4])); break;
+    case 2: out = times_i(rmul(c[7], sk[4])); break;
+    case 3: out = times_i(rmul(-c[8], sk[3]) - rmul(c[9], sk[4])); break;
+    case 4: out = times_i(rmul(c[8], sk[2]) - rmul(c[5], sk[0])); break;
+    case 5: out = times_i(rmul(c[9], sk[2]) - rmul(c[6], sk[0]) - rmul(c[7], sk[1])); break;
+    default: return;
+  }
+  double2* dst = q == 0 ? V.y0 : V.u[q - 1];
+  dst[r] = fromd2(out);
+}
+
+__global__ __launch_bounds__(kThreads) void m6_stage_b_kernel(M6Terms T, M6Vecs V, double scale, int dim, IterArgs a) {
+  if (a.check_stop && load_stopped(a.slot)) return;
+  const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const int r = (int)(t / kM6Lanes), q = (int)(t % kM6Lanes);
+  d2 acc = {0.0, 0.0};
+  if (r < dim) {
+#pragma unroll
+    for (int k = 0; k < kM6Terms; ++k) {
+      const d2* av = reinterpret_cast<const d2*>(T.m[k].val);
+      const d2* uv = reinterpret_cast<const d2*>(V.u[k]);
+      for (int e = T.m[k].rp[r] + q; e < T.m[k].rp[r + 1]; e += kM6Lanes) acc += cmul(av[e], uv[T.m[k].ci[e]]);
+    }
+  }
+#pragma unroll
+  for (int off = kM6Lanes / 2; off > 0; off >>= 1) {
     acc.x += __shfl_xor(acc.x, off, 64);
     acc.y += __shfl_xor(acc.y, off, 64);
   }
-  if (r < dim && q == 0) {
-    d2 v = cmul(tod2(alpha), acc);
-    if (accumulate) v += tod2(y[r]);
-    y[r] = fromd2(v);
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void lincomb_kernel(LinComb L, double2* __restrict__ out, int dim,
-                                                          const Slot* slot, int check_stop) {
-  if (check_stop && load_stopped(slot)) return;
-  const int r = blockIdx.x * kThreads + threadIdx.x;
-  if (r >= dim) return;
-  d2 v = {0.0, 0.0};
-  for (int j = 0; j < L.n; ++j) v += rmul(L.c[j], tod2(L.x[j][r]));
-  out[r] = fromd2(v);
-}
-
-// w_i = scale y - sigma w_{i-1} and the Newton update, y = (the Hermitian
-// exponent) w_{i-1} computed beforehand; one row per thread.
-__global__ __launch_bounds__(kThreads) void leja_update_kernel(const double2* __restrict__ y, double scale, int dim,
-                                                              IterArgs a) {
-  if (a.check_stop && load_stopped(a.slot)) return;
-  const int r = blockIdx.x * kThreads + threadIdx.x;
   double pw = 0.0, pv = 0.0;
-  if (r < dim) leja_row(a, r, rmul(scale, tod2(y[r])), pw, pv);
+  if (r < dim && q == 0) leja_row(a, r, rmul(scale, tod2(V.y0[r]) + acc), pw, pv);
   block_partials(a, pw, pv);
 }
 
@@ -891,26 +914,19 @@ hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, lon
   return hipGetLastError();
 }
 
-hipError_t launch_csr_axpy(const CsrDev& A, const double2* x, double2* y, double2 alpha, bool accumulate, int dim,
-                           const Slot* slot, int check_stop, hipStream_t s) {
+int m6_grid(int dim) { return (int)(((long long)dim * kM6Lanes + kThreads - 1) / kThreads); }
+
+hipError_t launch_m6_stage_a(const M6Terms& T, const double2* w, const M6Coef& C, const M6Vecs& V, int dim,
+                             const Slot* slot, int check_stop, hipStream_t s) {
   if (dim <= 0) return hipSuccess;
-  const long long threads = (long long)dim * kAxpyLanes;
-  csr_axpy_kernel<<<(unsigned)((threads + kThreads - 1) / kThreads), kThreads, 0, s>>>(A, x, y, alpha, accumulate ? 1 : 0,
-                                                                                      dim, slot, check_stop);
+  m6_stage_a_kernel<<<m6_grid(dim), kThreads, 0, s>>>(T, w, C, V, dim, slot, check_stop);
   return hipGetLastError();
 }
 
-hipError_t launch_lincomb(const LinComb& L, double2* out, int dim, const Slot* slot, int check_stop, hipStream_t s) {
+hipError_t launch_m6_stage_b(const M6Terms& T, const M6Vecs& V, double scale, int dim, const IterArgs& a,
+                             hipStream_t s) {
   if (dim <= 0) return hipSuccess;
-  if (L.n < 1 || L.n > kLinCombMax) return hipErrorInvalidValue;
-  lincomb_kernel<<<(dim + kThreads - 1) / kThreads, kThreads, 0, s>>>(L, out, dim, slot, check_stop);
-  return hipGetLastError();
-}
-
-int leja_update_grid(int dim) { return (dim + kThreads - 1) / kThreads; }
-
-hipError_t launch_leja_update(const double2* y, double scale, int dim, const IterArgs& a, hipStream_t s) {
-  leja_update_kernel<<<leja_update_grid(dim), kThreads, 0, s>>>(y, scale, dim, a);
+  m6_stage_b_kernel<<<m6_grid(dim), kThreads, 0, s>>>(T, V, scale, dim, a);
   return hipGetLastError();
 }
 
