@@ -8,7 +8,7 @@
 // one-workgroup kernel that follows reduces the partials in a fixed order and
 // writes the early-termination verdict for the next iteration to read, so the
 // host never waits.
-#include "kernels.h"
+#include "device_common.h"
 
 #include <algorithm>
 #include <cmath>
@@ -17,35 +17,7 @@
 namespace magnus {
 namespace {
 
-using d2 = double __attribute__((ext_vector_type(2)));
-
-constexpr int kThreads = 256;
-
-__device__ __forceinline__ d2 cmul(d2 a, d2 b) {
-  return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-__device__ __forceinline__ d2 rmul(double s, d2 a) { return d2{s * a.x, s * a.y}; }
-__device__ __forceinline__ d2 tod2(double2 v) { return d2{v.x, v.y}; }
-__device__ __forceinline__ double2 fromd2(d2 v) { return make_double2(v.x, v.y); }
-__device__ __forceinline__ double nrm2(d2 v) { return v.x * v.x + v.y * v.y; }
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of row blocks so rows that share gathered vector entries
-// share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int q = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
-  return x * q + min(x, rem) + k;
-}
-
-__device__ __forceinline__ int load_stopped(const Slot* s) {
-  return __hip_atomic_load(&s->stopped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
+using namespace dev;
 
 // Leja update for one row; y = (scale-folded) H_hat w at that row.
 __device__ __forceinline__ void leja_row(const IterArgs& a, int r, d2 y, double& pw, double& pv) {
@@ -124,20 +96,7 @@ __global__ __launch_bounds__(kDecideThreads) void leja_decide_kernel(IterArgs a,
   if (tid == 0) {
     double tw = 0.0, tv = 0.0;
     for (int w = 0; w < kDecideThreads / 64; ++w) { tw += red[0][w]; tv += red[1][w]; }
-    Slot* S = a.slot;
-    const double wn = sqrt(tw);
-    const double vn = a.first ? sqrt(tv) : S->vnorm;
-    const double prev = a.first ? a.d0abs * vn : S->prev_term;
-    const double term = a.dabs * wn;
-    const double est = term + prev;
-    const bool bad = !isfinite(tw) || !isfinite(vn);
-    if (bad) S->status |= 1;
-    S->vnorm = vn;
-    S->prev_term = term;
-    S->last_est = est;
-    S->iters_sub = a.first ? 1 : S->iters_sub + 1;
-    S->stopped = (bad || (a.early && est <= a.tol * vn)) ? 1 : 0;
-    S->iters_total += 1;
+    leja_verdict(a.slot, a.first, a.early, a.tol, a.dabs, a.d0abs, tw, tv);
   }
 }
 
