@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--workload", default="chain_n20",
                     choices=["chain_n20", "chain_n10", "dense_8192", "batched_dense_4096", "ragged_chains",
                              "adjoint_chain_n16", "adjoint_dense_4096", "accuracy_cost_dense",
-                             "accuracy_cost_sparse"],
+                             "accuracy_cost_sparse", "chain_sizes", "m6_chains"],
                     help="chain_n20 is the headline line; the others print one informational line each")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size heuristic for the CSR kernel")
     ap.add_argument("--bounds", choices=["gershgorin", "lanczos"], default="lanczos",
@@ -468,6 +468,57 @@ def other_workload(name: str, args):
         line.update({"metric": f"adjoint loss+gradient time vs forward ({what}, 400 Cf4 steps, 32 params)",
                      "value": ms_g / ms_f, "unit": "ratio", "gradient_ms": ms_g, "forward_ms": ms_f,
                      "loss": loss, "grad_norm": float(np.linalg.norm(grad))})
+    elif name == "chain_sizes":
+        # one state on chains of n = 13 ... 20 sites, Cf4: the default CSR mapping of each size
+        # (persistent kernel up to 4096 rows, then the grid path with its kernels chosen by size)
+        tau, sizes = 0.01, (13, 14, 15, 16, 17, 18, 19, 20)
+        per_n = {}
+        for n in sizes:
+            H1, H2 = inputs.chain_terms(n)
+            dim = 1 << n
+            ctx = B.Context(max_dim=dim, max_batch=1)
+            ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+            fn = np.vectorize(inputs.cos_field(2.0))(B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K))
+            psi = torch.from_numpy(inputs.random_states(dim, seed=1)).cuda()
+            opts = B.leja_opts(1e-13)
+            B.propagate(ctx, ham, B.CF4, tau, fn[:W], psi, opts=opts)
+            ms, (_, st) = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, fn[W:], psi, opts=opts, stats=True))
+            it_bytes = csr_iter_bytes(H1.nnz + H2.nnz, dim)
+            per_n[str(n)] = {"steps_per_s": K / (ms * 1e-3), "us_per_iteration": 1e3 * ms / st["iters"],
+                             "leja_iters_per_step": st["iters"] / K,
+                             "hv_gbps": it_bytes * st["iters"] / (ms * 1e-3) / 1e9}
+            ctx.close()
+            print(f"[bench] chain n={n}: {per_n[str(n)]['steps_per_s']:.0f} steps/s", file=sys.stderr, flush=True)
+        line.update({"metric": "Cf4 Magnus steps/sec, one state, chains n = 13..20 (1e-13 per exponential)",
+                     "value": per_n["16"]["steps_per_s"], "unit": "steps/s (n = 16)", "steps": K,
+                     "per_n": per_n})
+    elif name == "m6_chains":
+        # Method M6 on CSR terms (Section 2): K, P_1, P_2 assembled on the device once, the
+        # nested commutators applied as commutators of them, two passes per Leja iteration
+        tau, sizes = 0.01, (16, 20)
+        per_n = {}
+        for n in sizes:
+            H1, H2 = inputs.chain_terms(n)
+            dim = 1 << n
+            ctx = B.Context(max_dim=dim, max_batch=1)
+            ham = B.magnus_spectral_bounds_lanczos(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+            prep_ms, _ = _timed(lambda: B.magnus_csr_m6_prepare(ctx, ham))
+            fn = np.vectorize(inputs.cos_field(2.0))(B.magnus_quadrature_nodes(B.M6, 0.0, tau, W + K))
+            psi = torch.from_numpy(inputs.random_states(dim, seed=1)).cuda()
+            opts = B.leja_opts(1e-13)
+            B.propagate(ctx, ham, B.M6, tau, fn[:W], psi, opts=opts)
+            ctx.timing(True)
+            ms, (_, st) = _timed(lambda: B.propagate(ctx, ham, B.M6, tau, fn[W:], psi, opts=opts, stats=True))
+            kms, kn = ctx.timing_read(B.KERNEL_CSR_LEJA)
+            ctx.timing(False)
+            per_n[str(n)] = {"steps_per_s": K / (ms * 1e-3), "us_per_iteration": 1e3 * ms / st["iters"],
+                             "leja_iters_per_step": st["iters"] / K, "prepare_ms": prep_ms,
+                             "stage_b_kernel_avg_us": 1e3 * kms / max(kn, 1)}
+            ctx.close()
+            print(f"[bench] M6 chain n={n}: {per_n[str(n)]['steps_per_s']:.1f} steps/s", file=sys.stderr, flush=True)
+        line.update({"metric": "M6 Magnus steps/sec on CSR terms, chains n = 16 and 20 (1e-13 per exponential)",
+                     "value": per_n["20"]["steps_per_s"], "unit": "steps/s (n = 20)", "steps": K,
+                     "per_n": per_n})
     elif name in ("accuracy_cost_dense", "accuracy_cost_sparse"):
         # Figures 4 and 8 of Section 4 on this GPU: N = 2^12, error at t = 1 against an
         # M6 reference, each run with the Leja tolerance set to a tenth of the error it
