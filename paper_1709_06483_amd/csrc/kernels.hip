@@ -665,7 +665,11 @@ __global__ __launch_bounds__(kThreads) void m6_stage_a_kernel(M6Terms T, const d
 __global__ __launch_bounds__(kThreads) void m6_stage_b_kernel(M6Terms T, M6Vecs V, double scale, int dim, IterArgs a) {
   if (a.check_stop && load_stopped(a.slot)) return;
   const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
-  const int r = (int)(t / kM6Lanes), q = (int)(t % kM6Lanes);
+  // rows in reverse order: stage A ends on the last rows, whose matrix entries
+  // are still in the MALL when stage B starts on them (and stage B ends on the
+  // first rows, where the next iteration's stage A starts)
+  const int r0 = (int)(t / kM6Lanes), q = (int)(t % kM6Lanes);
+  const int r = r0 < dim ? dim - 1 - r0 : r0;
   d2 acc = {0.0, 0.0};
   if (r < dim) {
 #pragma unroll
