@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-m4", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
     ap.add_argument("--workload", default="chain_n20",
                     choices=["chain_n20", "chain_n10", "dense_8192", "batched_dense_4096", "ragged_chains",
                              "adjoint_chain_n16", "adjoint_dense_4096", "accuracy_cost_dense",

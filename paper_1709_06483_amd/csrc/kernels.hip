@@ -63,9 +63,12 @@ __device__ void block_partials(const IterArgs& a, double pw, double pv) {
 // fixed order, then the early-termination test of Section 3 (our reading:
 // stop once |d_i w_i| + |d_{i-1} w_{i-1}| <= tol |v|).  Every thread issues
 // all of its loads before summing, so the kernel costs about one memory
-// round trip.
-constexpr int kDecideThreads = 1024;
-constexpr int kDecidePer = 32;
+// round trip.  The kernel sits between every two iterations, so its own
+// dispatch and completion matter on small grids: four waves dispatch and
+// finish sooner than sixteen (measured, Cf4 on chains: n = 13 6,531 -> 7,548
+// steps/s, n = 16 3,579 -> 3,829, n = 20 unchanged).
+constexpr int kDecideThreads = 256;
+constexpr int kDecidePer = 16;
 // sum of p[0..n) over the workgroup's threads (each thread's loads all issued first)
 __device__ __forceinline__ double decide_sum(const double* p, int n, int tid) {
   double s = 0.0;
