@@ -399,13 +399,16 @@ int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch,
 #define MAGNUS_KERNEL_PERSIST    6  /* whole small-state propagations, one workgroup per state */
 #define MAGNUS_KERNEL_CSR_LEJA3  7  /* three-term CSR Leja iteration (assembled commutator) */
 
-/* enable = 1: from now on bracket every iteration kernel the context launches
- * with a pair of HIP events on the call's stream (previous records are
- * dropped); enable = 0: stop recording.  Errors: EINVAL, EHIP. */
+/* enable = k >= 1: from now on bracket every k-th launch of each kernel class
+ * (k = 1: every iteration kernel the context launches) with a pair of HIP
+ * events on the call's stream, previous records dropped; a larger k keeps the
+ * events' own cost (a few percent of a 150 us launch at k = 1) out of the
+ * launches in between.  enable = 0: stop recording.  Errors: EINVAL (k < 0),
+ * EHIP. */
 int magnus_timing(magnus_ctx* ctx, int32_t enable);
 
 /* Wait for the recorded events and report, for one kernel class, the summed
- * event-to-event time in milliseconds and the number of launches.
+ * event-to-event time in milliseconds and the number of bracketed launches.
  * Errors: EINVAL (bad class), EHIP. */
 int magnus_timing_read(magnus_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
 

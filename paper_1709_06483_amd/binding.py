@@ -214,11 +214,14 @@ class Context:
         """Let groups of states on dense terms use one assembled exponent per Leja iteration."""
         _check(lib().magnus_reserve_dense(self.handle, dim))
 
-    def timing(self, enable: bool):
-        _check(lib().magnus_timing(self.handle, int(bool(enable))))
+    def timing(self, enable: bool, stride: int = 1):
+        """Bracket every stride-th launch of each kernel class with HIP events (or stop)."""
+        if stride < 1:
+            raise ValueError("stride must be at least 1")
+        _check(lib().magnus_timing(self.handle, int(stride) if enable else 0))
 
     def timing_read(self, kind: int):
-        """(total milliseconds, launches) of one kernel class since timing was enabled."""
+        """(total milliseconds, bracketed launches) of one kernel class since timing was enabled."""
         t, n = C.c_double(), C.c_int64()
         _check(lib().magnus_timing_read(self.handle, kind, C.byref(t), C.byref(n)))
         return t.value, n.value

@@ -123,7 +123,8 @@ struct magnus_ctx {
   // magnus_autotune results, per CSR term pair (H1 row_ptr, dim): the variant code
   // of the single-state iteration and the states per multi-state pass
   std::map<std::pair<const void*, int64_t>, int> tuned_variant, tuned_group;
-  bool timing = false;
+  int timing = 0;  // 0 off, k >= 1: every k-th launch of each kernel class is bracketed
+  int64_t timing_seq[MAGNUS_KERNEL_CSR_LEJA3 + 1] = {};  // launches of each class since enabling
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
@@ -320,6 +321,7 @@ hipEvent_t next_event(magnus_ctx* ctx) {
 template <class F>
 hipError_t timed(magnus_ctx* ctx, int kind, hipStream_t s, F f) {
   if (!ctx->timing) return f();
+  if (ctx->timing_seq[kind]++ % ctx->timing != 0) return f();
   hipEvent_t a = next_event(ctx), b = next_event(ctx);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, s);
@@ -1788,13 +1790,15 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
 
 int magnus_timing(magnus_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(MAGNUS_EINVAL, "null context");
+  if (enable < 0) return fail(MAGNUS_EINVAL, "timing stride %d", enable);
   HIP_TRY(hipSetDevice(ctx->device));
   if (enable) {
     HIP_TRY(hipDeviceSynchronize());  // pooled events may still be pending
     ctx->records.clear();
     ctx->pool_used = 0;
+    for (auto& k : ctx->timing_seq) k = 0;
   }
-  ctx->timing = enable != 0;
+  ctx->timing = enable;
   return MAGNUS_OK;
 }
 

@@ -708,3 +708,24 @@ def test_streamed_tiles_small_and_degenerate(N, variant, monkeypatch):
     c.close()
     ref = oe.expmv_taylor(oracle_exponent(sp.csr_matrix(A1), sp.csr_matrix(A2), 0.7, -0.3, 0.02, 0.05), v)
     assert rel(w, ref) <= 20 * tol, N
+
+
+@pytest.mark.parametrize("stride", [1, 3])
+def test_kernel_timing_stride(stride):
+    """magnus_timing with stride k brackets every k-th launch of a kernel class: the
+    number of bracketed iteration launches is ceil(iterations / k)."""
+    H1, H2 = chain(12)
+    c = B.Context(max_dim=1 << 12)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+    v = dev(inputs.random_states(1 << 12, seed=5))
+    c.timing(True, stride=stride)
+    _, st = B.expmv_leja(c, ham, 1.0, 0.5, 0.0, 0.05, v, opts=B.leja_opts(1e-12, early_termination=False),
+                         stats=True)
+    ms, n = c.timing_read(B.KERNEL_CSR_LEJA)
+    c.timing(False)
+    assert st["iters"] > 3
+    assert n == -(-st["iters"] // stride)
+    assert ms > 0.0
+    with pytest.raises(ValueError):
+        c.timing(True, stride=0)
+    c.close()
