@@ -70,7 +70,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus {args.gpus}, "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (--gpus {args.gpus}, "
               f"WORLD_SIZE {world}); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

@@ -151,3 +151,15 @@ def test_method_nodes_are_gauss_legendre(method, q):
         assert np.allclose(t[n], 1.5 + n * 0.2 + 0.2 * (x + 1) / 2, rtol=0, atol=1e-15)
     with pytest.raises(B.MagnusError):
         B.magnus_method_nodes(9)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says so,
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
