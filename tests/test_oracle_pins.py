@@ -260,3 +260,67 @@ def test_fig1_printed_slopes(golden_dir):
         taus = sorted(paper[m], reverse=True)[1:]
         sl = [math.log2(paper[m][taus[i]] / paper[m][taus[i + 1]]) for i in range(len(taus) - 1)]
         assert all(abs(s - order) < 0.35 for s in sl), (m, sl)
+
+
+# -- P1 on commutator exponents: the Taylor path through lazy commutators -----
+@pytest.mark.parametrize("n", [8, 10])
+@pytest.mark.parametrize("method", ["M4", "M6"])
+@pytest.mark.parametrize("tau", [0.01, 0.1, 0.3])
+def test_taylor_on_commutator_exponents_matches_eig(n, method, tau):
+    """oracle-T applies the M4 and M6 exponents (Section 2, Methods M4 and M6)
+    as matvecs through the lazy commutators (X(Yv) - Y(Xv), nested for M6);
+    oracle-E forms the same exponent densely (XY - YX) and diagonalises it.
+    The two code paths share only the stored terms; both must agree with each
+    other and with scipy's dense expm to rounding.  tau = 0.1 and 0.3 force
+    several Taylor substeps (s >= 3), tau = 0.01 one."""
+    H1, H2 = inputs.chain_terms(n)
+    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), lambda t: math.cos(2 * t))
+    v = inputs.random_states(1 << n, seed=7)
+    (Om,) = mg.METHODS[method](P, 0.37, tau)
+    s, _, _ = oe.taylor_plan(Om.norm_bound())
+    assert (s >= 3) == (tau >= 0.1)
+    t = oe.expmv_taylor(Om, v)
+    e = oe.expmv_eig(Om, v)
+    ref = sla.expm(Om.dense()) @ v
+    assert np.linalg.norm(t - e) <= 1e-14 * np.linalg.norm(e)
+    assert np.linalg.norm(t - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("method", ["M4", "M6"])
+def test_commutator_norm_bounds_dominate_true_norm(method):
+    """The substep count of oracle-T rests on norm_bound() being an upper bound
+    of the spectral norm; check it for a bare commutator, a nested one and the
+    full exponents against the 2-norm of their dense forms."""
+    n = 8
+    H1, H2 = inputs.chain_terms(n)
+    A, B = Mat(H1.to_scipy()), Mat(H2.to_scipy())
+    Ad, Bd = H1.to_scipy().toarray(), H2.to_scipy().toarray()
+    C = Comm(A, B)
+    Cd = Ad @ Bd - Bd @ Ad
+    assert np.abs(C.dense() - Cd).max() == 0
+    w = inputs.random_states(1 << n, seed=8)
+    assert np.linalg.norm(C.matvec(w) - Cd @ w) <= 1e-13 * np.linalg.norm(Cd @ w)
+    assert C.norm_bound() >= np.linalg.norm(Cd, 2)
+    nested = Comm(A, Lin([(2.0, B), (1.0, C)]))
+    assert nested.norm_bound() >= np.linalg.norm(nested.dense(), 2)
+    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), lambda t: math.cos(2 * t))
+    (Om,) = mg.METHODS[method](P, 0.37, 0.1)
+    assert Om.norm_bound() >= np.linalg.norm(Om.dense(), 2)
+
+
+def test_planted_commutator_matvec_sign_is_caught():
+    """A commutator applied as X(Yv) + Y(Xv) (the anticommutator) must break
+    the agreement between the matvec and the dense path above."""
+    n = 8
+    H1, H2 = inputs.chain_terms(n)
+    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), lambda t: math.cos(2 * t))
+    (Om,) = mg.exponents_m4(P, 0.37, 0.1)
+
+    class Anti(Comm):
+        def matvec(self, v):
+            return self.X.matvec(self.Y.matvec(v)) + self.Y.matvec(self.X.matvec(v))
+
+    wrong = Lin([(c, Anti(X.X, X.Y) if isinstance(X, Comm) else X) for c, X in Om.terms])
+    v = inputs.random_states(1 << n, seed=7)
+    e = oe.expmv_eig(Om, v)
+    assert np.linalg.norm(oe.expmv_taylor(wrong, v) - e) > 1e-8
