@@ -60,8 +60,15 @@ def main():
                              "accuracy_cost_sparse", "chain_sizes", "m6_chains"],
                     help="chain_n20 is the headline line; the others print one informational line each")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size heuristic for the CSR kernel")
-    ap.add_argument("--timing-stride", type=int, default=8,
-                    help="the timed region brackets every k-th iteration launch with HIP events (1: every launch)")
+    ap.add_argument("--timing-stride", type=int, default=7,
+                    help="the timed region brackets every k-th iteration launch with HIP events (1: every launch); "
+                         "keep it coprime with the planned degree so the sampled launches cover every iteration "
+                         "position of an exponential")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="the K timed steps are run this many times from the same post-warmup state; "
+                         "value is K over the median time")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the compact batched, ragged and adjoint measurements appended to the line")
     ap.add_argument("--bounds", choices=["gershgorin", "lanczos"], default="lanczos",
                     help="spectral enclosures of the terms: rigorous Gershgorin discs or Lanczos estimates")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -121,9 +128,11 @@ def main():
     if tune:
         print(f"[bench] autotune: {tune['variant_name']} "
               f"({', '.join(f'{k}: {v:.1f} us' for k, v in tune['variant_us'].items())})", file=sys.stderr, flush=True)
-    W, K = args.warmup, args.steps
+    W, K, R = args.warmup, args.steps, max(1, args.reps)
 
     def run(method: str, tol_e: float):
+        """W warmup steps, then R timed runs of the next K steps, each from the
+        post-warmup state; returns the median time and the stats of that run."""
         mid = B.METHODS[method]
         tn = B.magnus_quadrature_nodes(mid, 0.0, tau, W + K)
         fn = np.vectorize(f)(tn)
@@ -131,43 +140,52 @@ def main():
         opts = B.leja_opts(tol_e)
         if W:
             B.propagate(ctx, ham, mid, tau, fn[:W], psi, opts=opts)
+        psi_w = psi.clone()
         torch.cuda.synchronize()
         ctx.timing(True, stride=args.timing_stride)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        ev0.record()
-        _, st = B.propagate(ctx, ham, mid, tau, fn[W:], psi, opts=opts, stats=True)
-        ev1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = ev0.elapsed_time(ev1)
+        runs = []
+        for _ in range(R):
+            psi.copy_(psi_w)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            ev0.record()
+            _, st = B.propagate(ctx, ham, mid, tau, fn[W:], psi, opts=opts, stats=True)
+            ev1.record()
+            torch.cuda.synchronize()
+            runs.append((ev0.elapsed_time(ev1), time.perf_counter() - t0, st))
         kinds = {"leja": B.KERNEL_CSR_LEJA, "split": B.KERNEL_CSR_SPLIT, "comm": B.KERNEL_CSR_COMM,
                  "leja3": B.KERNEL_CSR_LEJA3}
         kt = {k: ctx.timing_read(v) for k, v in kinds.items()}
         ctx.timing(False)
         ctx.check()
-        return ms, wall, st, kt
+        runs.sort(key=lambda r: r[0])
+        ms, wall, st = runs[len(runs) // 2]
+        return ms, wall, st, kt, [r[0] for r in runs]
 
     out = {}
     # Cf4: two exponentials per step, tolerance budget split over the 500-step run
     tol_cf4 = cfg["budget_tol"] / (2 * cfg_steps)
-    ms, wall, st, kt = run("CF4", tol_cf4)
-    print(f"[bench] CF4 {K} steps: {ms:.1f} ms (wall {wall:.2f}s), iters {st['iters']}/{st['planned_iters']}",
-          file=sys.stderr, flush=True)
+    ms, wall, st, kt, all_ms = run("CF4", tol_cf4)
+    print(f"[bench] CF4 {K} steps x {R}: median {ms:.1f} ms (runs {', '.join(f'{x:.1f}' for x in all_ms)}), "
+          f"iters {st['iters']}/{st['planned_iters']}", file=sys.stderr, flush=True)
     it_bytes = csr_iter_bytes(nnz_total, dim)
     # every Leja iteration of the Cf4 run is one launch of the iteration kernel; the
-    # events bracket every timing_stride-th of them (the average is over those)
+    # events bracket every timing_stride-th of them.  The first iteration of each
+    # substep reads no Newton sum p (16 B per row less), so the bytes per sampled
+    # launch are the run's average over all iterations (the stride is coprime with
+    # the planned degree, so the samples cover every iteration position alike).
     k_ms, k_timed = kt["leja"]
     avg_ms = k_ms / max(k_timed, 1)
-    bytes_per_launch = it_bytes
+    bytes_per_launch = (st["iters"] * it_bytes - st["substeps"] * 16 * dim) / max(st["iters"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     steps_per_s = K / (ms * 1e-3)
-    hv_gbps = it_bytes * st["iters"] / (ms * 1e-3) / 1e9
+    hv_gbps = bytes_per_launch * st["iters"] / (ms * 1e-3) / 1e9
 
     if not args.no_m4:
         tol_m4 = cfg["budget_tol"] / cfg_steps
-        ms4, wall4, st4, kt4 = run("M4", tol_m4)
-        print(f"[bench] M4 {K} steps: {ms4:.1f} ms, iters {st4['iters']}/{st4['planned_iters']}",
+        ms4, wall4, st4, kt4, _ = run("M4", tol_m4)
+        print(f"[bench] M4 {K} steps: median {ms4:.1f} ms, iters {st4['iters']}/{st4['planned_iters']}",
               file=sys.stderr, flush=True)
         m4b = comm_iter_bytes(nnz_total, dim)
         out["m4"] = {
@@ -181,9 +199,9 @@ def main():
         }
         # M4 again with K = i[H1, H2] assembled on the device: one three-term pass per iteration
         kms, _ = _timed(lambda: B.magnus_csr_commutator(ctx, ham))
-        ms5, wall5, st5, kt5 = run("M4", tol_m4)
-        print(f"[bench] M4 (assembled commutator) {K} steps: {ms5:.1f} ms, iters {st5['iters']}", file=sys.stderr,
-              flush=True)
+        ms5, wall5, st5, kt5, _ = run("M4", tol_m4)
+        print(f"[bench] M4 (assembled commutator) {K} steps: median {ms5:.1f} ms, iters {st5['iters']}",
+              file=sys.stderr, flush=True)
         out["m4_assembled_commutator"] = {
             "steps_per_s": K / (ms5 * 1e-3),
             "ms_per_step": ms5 / K,
@@ -193,9 +211,23 @@ def main():
         }
 
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(H1, H2, f, tau, psi0, args.cpu_sample_steps)
+        nchk = args.cpu_sample_steps
+        cpu, ref = cpu_baseline(H1, H2, f, tau, psi0, nchk)
         print(f"[bench] cpu oracle: {cpu['value']:.3f} steps/s", file=sys.stderr, flush=True)
+        # the same first steps on the GPU (untimed; same enclosures, tolerance and kernels)
+        fchk = np.vectorize(f)(B.magnus_quadrature_nodes(B.CF4, 0.0, tau, nchk))
+        psi = torch.from_numpy(psi0).cuda()
+        B.propagate(ctx, ham, B.CF4, tau, fchk, psi, opts=B.leja_opts(tol_cf4))
+        got = psi.cpu().numpy()
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        # the run's 1e-10 budget scaled to the steps compared
+        allowed = cfg["budget_tol"] * nchk / cfg_steps
+        accuracy = {"err_vs_oracle": err, "steps_compared": nchk, "allowed": allowed,
+                    "oracle": "Cf4 with truncated-Taylor exponentials (a priori remainder 1e-17), FP64"}
+        print(f"[bench] error vs oracle after {nchk} steps: {err:.3e} (allowed {allowed:.1e})", file=sys.stderr,
+              flush=True)
 
     code = int(os.environ.get("MAGNUS_CSR_VARIANT", "0") or 0) or (tune["variant"] if tune else 0)
     kernel = CSR_KERNEL_NAMES.get(code, "unknown")
@@ -235,12 +267,20 @@ def main():
             "avg_launch_us": avg_ms * 1e3,
         },
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "timing": {"reps": R, "run_ms": all_ms, "statistic": "median"},
         "device": torch.cuda.get_device_name(0),
         "autotune": tune,
     }
     line.update(out)
-    print(json.dumps(line), flush=True)
     ctx.close()
+    if not args.no_extras:
+        line["extras"] = compact_extras(args)
+    print(json.dumps(line), flush=True)
+    if accuracy is not None and not accuracy["err_vs_oracle"] <= accuracy["allowed"]:
+        print(f"[bench] error vs oracle {accuracy['err_vs_oracle']:.3e} exceeds {accuracy['allowed']:.1e}",
+              file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 CSR_KERNEL_NAMES = {0: "csr2_wave_kernel<8, kLeja>", 1: "csr2_iter_kernel<64, kLeja>", 2: "csr2_rowlane_kernel<64, kLeja>",
@@ -314,8 +354,9 @@ def _timed(fn):
     return e0.elapsed_time(e1), out
 
 
-def other_workload(name: str, args):
-    """Informational measurements of the other workloads (one JSON line each)."""
+def other_workload(name: str, args, emit: bool = True):
+    """Informational measurements of the other workloads (one JSON line each;
+    with emit=False the line is returned instead of printed)."""
     import numpy as np
     import torch
 
@@ -389,16 +430,17 @@ def other_workload(name: str, args):
                           "leja_iters_per_step": st4["iters"] / K, "commutator_ms": gms,
                           "commutator_gemm_tflops": 8.0 * dim ** 3 / (gms * 1e-3) / 1e12}
     elif name == "batched_dense_4096":
-        N, Bn, tau = 4096, 256, 0.005
-        H0 = inputs.powerlaw_hermitian(N, 1.5, 31)
-        V = inputs.powerlaw_hermitian(N, 1.5, 32)
+        cfg = inputs.CONFIGS["batched_dense_4096"]
+        N, Bn, tau = cfg["N"], cfg["batch"], cfg["tau"]
+        H0 = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["H0"])
+        V = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["V"])
         ctx = B.Context(max_dim=N, max_batch=Bn)
         ctx.reserve_dense(N)
         ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H0, V))
-        psi = torch.from_numpy(inputs.random_states(N, seed=30, batch=Bn)).cuda()
-        f = inputs.sin_field(1.0)
+        psi = torch.from_numpy(inputs.random_states(N, seed=cfg["seeds"]["psi"], batch=Bn)).cuda()
+        f = inputs.sin_field(cfg["omega"])
         fn = np.vectorize(f)(B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K))
-        tol_e = 1e-10 / (2 * 200)
+        tol_e = cfg["budget_tol"] / (2 * cfg["nsteps"])
         B.propagate(ctx, ham, B.CF4, tau, fn[:W], psi, opts=B.leja_opts(tol_e))
         ctx.timing(True)
         ms, (_, st) = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, fn[W:], psi, opts=B.leja_opts(tol_e),
@@ -418,19 +460,20 @@ def other_workload(name: str, args):
                      "mfma_util_vs_78.6TF": flops / max(kms * 1e-3, 1e-12) / 78.6e12,
                      "leja_iters_per_step": st["iters"] / (K * Bn)})
     elif name == "ragged_chains":
-        tau, sizes, per = 0.01, (12, 14, 16, 18), 16
+        cfg = inputs.CONFIGS["ragged_chains"]
+        tau, sizes, per = cfg["tau"], cfg["sizes"], cfg["per_size"]
         ctx = B.Context(max_dim=1 << max(sizes), max_batch=per)
         probs = []
         for n in sizes:
-            H1, H2 = inputs.chain_terms(n)
+            H1, H2 = inputs.chain_terms(n, cfg["J"], cfg["Delta"])
             ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
             if not args.no_autotune and (1 << n) > 4096:
                 B.magnus_autotune(ctx, ham, batch=per)
-            psi = torch.from_numpy(inputs.random_states(1 << n, seed=300 + n, batch=per)).cuda()
+            psi = torch.from_numpy(inputs.random_states(1 << n, seed=cfg["psi_seed_base"] + n, batch=per)).cuda()
             t = B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K)
-            fn = np.stack([np.vectorize(inputs.cos_field(2.0, 1.0 + k / per))(t) for k in range(per)])
+            fn = np.stack([np.vectorize(inputs.cos_field(cfg["omega"], 1.0 + k / per))(t) for k in range(per)])
             probs.append((ham, psi, fn))
-        tol_e = 1e-10 / (2 * 100)
+        tol_e = cfg["budget_tol"] / (2 * cfg["nsteps"])
         warm = [(ham, psi, fn[:, :W]) for ham, psi, fn in probs]
         timed = [(ham, psi, fn[:, W:]) for ham, psi, fn in probs]
         if W:
@@ -446,25 +489,27 @@ def other_workload(name: str, args):
                      "instance_steps_per_s": len(sizes) * per * K / (ms * 1e-3)})
     elif name in ("adjoint_chain_n16", "adjoint_dense_4096"):
         from paper_1709_06483_amd import adjoint as A
-        P, T, nsteps = 32, 2.0, 400
+        cfg = inputs.CONFIGS[name]
+        P, T, nsteps = cfg["params"], cfg["T"], cfg["nsteps"]
         tau = T / nsteps
         if name == "adjoint_chain_n16":
-            dim = 1 << 16
-            H1, H2 = inputs.chain_terms(16)
+            dim = 1 << cfg["n"]
+            H1, H2 = inputs.chain_terms(cfg["n"], cfg["J"], cfg["Delta"])
             ctx = B.Context(max_dim=dim, max_batch=2)
             ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
             what = "n=16 chain"
         else:
-            dim = 4096
+            dim = cfg["N"]
             ctx = B.Context(max_dim=dim, max_batch=2)
             ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(
-                inputs.powerlaw_hermitian(dim, 1.5, 20), inputs.powerlaw_hermitian(dim, 1.5, 21)))
+                inputs.powerlaw_hermitian(dim, cfg["alpha"], cfg["seeds"]["H0"]),
+                inputs.powerlaw_hermitian(dim, cfg["alpha"], cfg["seeds"]["V"])))
             what = "dense 4096"
-        theta = inputs.fourier_theta(P, 40)
-        d0 = torch.from_numpy(inputs.random_states(dim, seed=41)).cuda()
-        dt = torch.from_numpy(inputs.random_states(dim, seed=42)).cuda()
+        theta = inputs.fourier_theta(P, cfg["theta_seed"])
+        d0 = torch.from_numpy(inputs.random_states(dim, seed=cfg["psi_seed"])).cuda()
+        dt = torch.from_numpy(inputs.random_states(dim, seed=cfg["target_seed"])).cuda()
         prob = A.ControlProblem.with_basis(ctx, ham, tau, nsteps, inputs.fourier_basis(P, T), d0, dt, every_k=20,
-                                           opts=B.leja_opts(1e-10 / (2 * nsteps)))
+                                           opts=B.leja_opts(cfg["budget_tol"] / (2 * nsteps)))
         prob.loss_and_grad(theta)
         ms_g, (loss, grad) = _timed(lambda: prob.loss_and_grad(theta))
         f = prob.basis_nodes @ theta
@@ -578,7 +623,81 @@ def other_workload(name: str, args):
                      "value": cf4, "unit": "ms", "higher_is_better": False,
                      "paper_k80_seconds_to_1e-10": paper, "reference_ms": ms_ref,
                      "ms_to_reach": best, "points": points})
+    if "ctx" in locals():
+        ctx.close()
+    if not emit:
+        return line
     print(json.dumps(line), flush=True)
+
+
+def compact_extras(args):
+    """Short driver-visible runs of the batched, ragged and adjoint workloads:
+    each against its plain (one state, one call) counterpart, and the adjoint
+    gradient against central differences of the device loss."""
+    import copy
+
+    import numpy as np
+    import torch
+
+    from paper_1709_06483_amd import adjoint as A
+    from paper_1709_06483_amd import binding as B
+    from paper_1709_06483_amd import inputs
+
+    ex = {}
+    t0 = time.perf_counter()
+    a = copy.copy(args)
+    a.steps, a.warmup = 4, 1
+    d = other_workload("batched_dense_4096", a, emit=False)
+    ex["batched_dense_4096"] = {k: d[k] for k in ("steps", "state_steps_per_s", "plain_state_steps_per_s",
+                                                  "batched_vs_plain", "mfma_tflops", "mfma_util_vs_78.6TF",
+                                                  "gemm_avg_us")}
+    print(f"[bench] extras: batched dense 4096 x 256: {d['batched_vs_plain']:.1f} x plain, "
+          f"{d['mfma_tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    a.steps, a.warmup = 20, 2
+    d = other_workload("ragged_chains", a, emit=False)
+    ex["ragged_chains"] = {k: d[k] for k in ("steps", "value", "instance_steps_per_s", "plain_instance_steps_per_s",
+                                             "batched_vs_plain")}
+    ex["ragged_chains"]["steps_per_s"] = ex["ragged_chains"].pop("value")
+    print(f"[bench] extras: ragged chains: {d['batched_vs_plain']:.2f} x plain", file=sys.stderr, flush=True)
+
+    # adjoint on the n = 16 chain, 400 Cf4 steps, 32 parameters; central differences
+    # of the device loss on two of them (early termination off, so the loss is smooth)
+    cfg = inputs.CONFIGS["adjoint_chain_n16"]
+    P, T, nsteps, eps = cfg["params"], cfg["T"], cfg["nsteps"], 1e-5
+    tau, dim = T / nsteps, 1 << cfg["n"]
+    H1, H2 = inputs.chain_terms(cfg["n"], cfg["J"], cfg["Delta"])
+    ctx = B.Context(max_dim=dim, max_batch=2)
+    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    theta = inputs.fourier_theta(P, cfg["theta_seed"])
+    d0 = torch.from_numpy(inputs.random_states(dim, seed=cfg["psi_seed"])).cuda()
+    dt = torch.from_numpy(inputs.random_states(dim, seed=cfg["target_seed"])).cuda()
+    opts = B.leja_opts(cfg["budget_tol"] / (2 * nsteps), early_termination=False)
+    prob = A.ControlProblem.with_basis(ctx, ham, tau, nsteps, inputs.fourier_basis(P, T), d0, dt, every_k=20,
+                                       opts=opts)
+    prob.loss_and_grad(theta)
+    ms_g, (loss, grad) = _timed(lambda: prob.loss_and_grad(theta))
+
+    def dev_loss(th):
+        psi = d0.clone()
+        B.propagate(ctx, ham, B.CF4, tau, prob.basis_nodes @ th, psi, opts=opts)
+        return 1.0 - abs(complex(torch.vdot(dt, psi))) ** 2
+
+    psi = d0.clone()
+    ms_f, _ = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, prob.basis_nodes @ theta, psi, opts=opts))
+    fd = {}
+    for k in (0, 7):
+        e = np.zeros(P)
+        e[k] = eps
+        fd[k] = (dev_loss(theta + e) - dev_loss(theta - e)) / (2 * eps)
+    ctx.close()
+    ex["adjoint_chain_n16"] = {"gradient_ms": ms_g, "forward_ms": ms_f, "gradient_vs_forward": ms_g / ms_f,
+                               "loss": loss, "fd_params": [k + 1 for k in fd],
+                               "max_abs_grad_minus_fd": max(abs(grad[k] - v) for k, v in fd.items()),
+                               "fd_eps": eps}
+    print(f"[bench] extras: adjoint n=16: {ms_g / ms_f:.2f} x forward, |grad - fd| "
+          f"{ex['adjoint_chain_n16']['max_abs_grad_minus_fd']:.2e}; extras took {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    return ex
 
 
 def cpu_baseline(H1, H2, f, tau, psi0, nsample: int):
@@ -591,11 +710,11 @@ def cpu_baseline(H1, H2, f, tau, psi0, nsample: int):
     P = mg.two_term(H1.to_scipy(), H2.to_scipy(), f)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        mg.propagate("CF4", P, tau, nsample, psi0, expm="taylor")
+        ref = mg.propagate("CF4", P, tau, nsample, psi0, expm="taylor")
         dt = time.perf_counter() - t0
-    return {"value": nsample / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nsample} Cf4 steps of chain_n20 (oracle-T: Taylor series, a priori remainder "
-                      f"1e-17, scipy CSR products, 1 thread), {dt:.1f} s"}
+    return ({"value": nsample / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+             "sample": f"first {nsample} Cf4 steps of chain_n20 (oracle-T: Taylor series, a priori remainder "
+                       f"1e-17, scipy CSR products, 1 thread), {dt:.1f} s"}, ref)
 
 
 if __name__ == "__main__":

@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave
     const d2* v1 = reinterpret_cast<const d2*>(t1.val);
     const d2* v2 = reinterpret_cast<const d2*>(t2.val);
     d2 acc1 = {0.0, 0.0}, acc2 = {0.0, 0.0};
-    const bool keep = base1 + base2 < keep_entries;  // uniform over the wave
+    const bool keep = (long long)base1 + base2 < keep_entries;  // uniform over the wave (no int overflow)
     for (int c0 = 0; c0 < total; c0 += CAPW) {
       const int cn = min(CAPW, total - c0);
       int col[U];

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kThreads, 5) void csr3_wave_kernel(CsrDev t1, CsrDe
     d2 acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     // the front of the matrix is read with normal loads and stays in the MALL
     // until the next iteration; the rest streams through (uniform per wave)
-    const bool keep = base[0] + base[1] + base[2] < keep_entries;
+    const bool keep = (long long)base[0] + base[1] + base[2] < keep_entries;  // no int overflow
     for (int c0 = 0; c0 < total; c0 += CAPW) {
       const int cn = min(CAPW, total - c0);
       int col[U];

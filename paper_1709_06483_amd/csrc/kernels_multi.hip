@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev 
     const int base1 = srp[wv][0][0], n1 = srp[wv][0][nrows] - base1;
     const int base2 = srp[wv][1][0], n2 = srp[wv][1][nrows] - base2;
     const int total = n1 + n2;
-    const bool keep = base1 + base2 < keep_entries;  // uniform over the wave
+    const bool keep = (long long)base1 + base2 < keep_entries;  // uniform over the wave (no int overflow)
     for (int c0 = 0; c0 < total; c0 += CAPW) {
       const int cn = min(CAPW, total - c0);
       int col[U];

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
   // terms together are copied with normal loads, the others non-temporal.
   auto issue = [&](const Tile& T, int c0, int b) {
     const int cn = min(kSCap, T.total - c0);
-    const bool keep = T.base1 + T.base2 < keep_entries;
+    const bool keep = (long long)T.base1 + T.base2 < keep_entries;  // no int overflow
 #pragma unroll 1
     for (int u = 0; u < kSU; ++u) {
       if (u * 64 < cn) {

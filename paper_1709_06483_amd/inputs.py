@@ -238,4 +238,20 @@ CONFIGS = {
     "dense_8192": dict(kind="dense_powerlaw", N=8192, alpha=1.5, omega=1.0, field="sin",
                        seeds=dict(H0=20, V=21, psi=22), tau=0.005, nsteps=200, t0=0.0,
                        budget_tol=1e-10),
+    # 256 states on the dense construction at N = 4096 (one FP64-MFMA GEMM per
+    # Leja iteration); step count and tau unstated, taken from dense_8192
+    "batched_dense_4096": dict(kind="batched", N=4096, alpha=1.5, omega=1.0, field="sin", batch=256,
+                               seeds=dict(H0=31, V=32, psi=30), tau=0.005, nsteps=200, t0=0.0,
+                               budget_tol=1e-10),
+    # chains of 12, 14, 16 and 18 sites, 16 instances each: instance k has the
+    # field amplitude 1 + k/16 on cos(2t) and its own initial state (seed
+    # 300 + n, one draw of 16 states); step count and tau taken from chain_n10
+    "ragged_chains": dict(kind="ragged", sizes=(12, 14, 16, 18), per_size=16, J=1.0, Delta=0.5, omega=2.0,
+                          field="cos", psi_seed_base=300, tau=0.01, nsteps=100, t0=0.0, budget_tol=1e-10),
+    # optimal control: f(t) = sum_{k<=32} theta_k sin(k pi t / T), theta ~ N(0, 0.1^2)
+    # (seed 40), T = 2, 400 Cf4 steps, loss 1 - |<psi_target, psi(T)>|^2
+    "adjoint_chain_n16": dict(kind="adjoint", n=16, J=1.0, Delta=0.5, params=32, theta_seed=40, T=2.0,
+                              nsteps=400, psi_seed=41, target_seed=42, budget_tol=1e-10),
+    "adjoint_dense_4096": dict(kind="adjoint", N=4096, alpha=1.5, seeds=dict(H0=20, V=21), params=32,
+                               theta_seed=40, T=2.0, nsteps=400, psi_seed=41, target_seed=42, budget_tol=1e-10),
 }
