@@ -1,0 +1,204 @@
+"""Parity at the full sizes of the measured workloads, in the launch
+configurations the benchmark times, against the CPU oracle (truncated Taylor
+exponentials with numpy/scipy products) or, for gradients, against central
+differences of the device loss.
+
+* dense N = 8192 (power-law H0 + sin(t) V): two-term Cf4 steps (most rows past
+  the MALL-resident front, read non-temporally), Cf4 with the exponent
+  assembled, M4 with K = i[H1, H2] assembled;
+* 256 states on dense N = 4096 (the FP64-MFMA GEMM iteration), sampled columns;
+* the ragged batch of chains n = 12, 14, 16, 18 x 16 instances in one call,
+  sampled instances;
+* chain n = 20 under the Lanczos enclosures the benchmark uses, more steps;
+* the adjoint gradient of 400 Cf4 steps with 32 Fourier parameters on the
+  n = 16 chain and on dense N = 4096, against central differences.
+
+Tolerance: each exponential is planned for tol_e (the 1e-10 budget of the
+workload's full run split over its exponentials); results must agree within
+50 tol_e per exponential compared, as the other full-size tests.
+"""
+import numpy as np
+import pytest
+
+from oracle import magnus as mg
+from paper_1709_06483_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected only where a GPU exists
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1709_06483_amd import adjoint as A  # noqa: E402
+from paper_1709_06483_amd import binding as B  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def nodes(method, f, t0, tau, nsteps):
+    return np.vectorize(f)(B.magnus_quadrature_nodes(B.METHODS[method], t0, tau, nsteps))
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dense8192():
+    cfg = inputs.CONFIGS["dense_8192"]
+    N = cfg["N"]
+    H0 = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["H0"])
+    V = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["V"])
+    return cfg, H0, V
+
+
+def test_dense_8192_two_term_assembled_and_m4(dense8192):
+    cfg, H0, V = dense8192
+    N, tau = cfg["N"], cfg["tau"]
+    f = inputs.sin_field(cfg["omega"])
+    psi0 = inputs.random_states(N, seed=cfg["seeds"]["psi"])
+    tol_e = cfg["budget_tol"] / (2 * cfg["nsteps"])
+    ctx = B.Context(max_dim=N)
+    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H0, V))
+    P = mg.two_term(H0, V, f)
+    ref = mg.propagate("CF4", P, tau, 2, psi0, expm="taylor")
+    # two-term GEMV iteration (no assembly buffer reserved)
+    psi = torch.from_numpy(psi0).cuda()
+    B.propagate(ctx, ham, B.CF4, tau, nodes("CF4", f, 0.0, tau, 2), psi, opts=B.leja_opts(tol_e))
+    e2 = rel(psi.cpu().numpy(), ref)
+    # the exponent assembled once per exponential, one-term GEMV iterations
+    ctx.reserve_dense(N)
+    psi = torch.from_numpy(psi0).cuda()
+    B.propagate(ctx, ham, B.CF4, tau, nodes("CF4", f, 0.0, tau, 2), psi, opts=B.leja_opts(tol_e))
+    e1 = rel(psi.cpu().numpy(), ref)
+    say(f"dense 8192 Cf4 2 steps: two-term {e2:.3e}, assembled {e1:.3e} (allowed {50 * tol_e * 4:.1e})")
+    assert e2 <= 50 * tol_e * 4 and e1 <= 50 * tol_e * 4
+    # Method M4 with K = i[H1, H2] assembled by the FP64-MFMA GEMM
+    B.magnus_dense_commutator(ctx, ham)
+    ref4 = mg.propagate("M4", P, tau, 1, psi0, expm="taylor")
+    psi = torch.from_numpy(psi0).cuda()
+    B.propagate(ctx, ham, B.M4, tau, nodes("M4", f, 0.0, tau, 1), psi, opts=B.leja_opts(2 * tol_e))
+    e4 = rel(psi.cpu().numpy(), ref4)
+    say(f"dense 8192 M4 1 step (K assembled): {e4:.3e}")
+    assert e4 <= 50 * 2 * tol_e
+    ctx.close()
+
+
+def test_batched_dense_4096_x256_sampled_columns():
+    cfg = inputs.CONFIGS["batched_dense_4096"]
+    N, Bn, tau = cfg["N"], cfg["batch"], cfg["tau"]
+    H0 = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["H0"])
+    V = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["V"])
+    f = inputs.sin_field(cfg["omega"])
+    psi0 = inputs.random_states(N, seed=cfg["seeds"]["psi"], batch=Bn)
+    tol_e = cfg["budget_tol"] / (2 * cfg["nsteps"])
+    ctx = B.Context(max_dim=N, max_batch=Bn)
+    ctx.reserve_dense(N)
+    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H0, V))
+    psi = torch.from_numpy(psi0).cuda()
+    ctx.timing(True)
+    B.propagate(ctx, ham, B.CF4, tau, nodes("CF4", f, 0.0, tau, 2), psi, opts=B.leja_opts(tol_e))
+    _, gemms = ctx.timing_read(B.KERNEL_DENSE_MFMA)
+    ctx.timing(False)
+    assert gemms > 0  # the batch ran as FP64-MFMA GEMM iterations
+    got = psi.cpu().numpy()
+    P = mg.two_term(H0, V, f)
+    for c in (0, 131, 255):
+        ref = mg.propagate("CF4", P, tau, 2, psi0[c], expm="taylor")
+        e = rel(got[c], ref)
+        say(f"dense 4096 x 256, column {c}, 2 Cf4 steps: {e:.3e}")
+        assert e <= 50 * tol_e * 4
+    ctx.close()
+
+
+def test_ragged_chains_12_to_18_x16_sampled_instances():
+    cfg = inputs.CONFIGS["ragged_chains"]
+    tau, per, nsteps = cfg["tau"], cfg["per_size"], 3
+    tol_e = cfg["budget_tol"] / (2 * cfg["nsteps"])
+    ctx = B.Context(max_dim=1 << max(cfg["sizes"]), max_batch=per)
+    probs, host = [], []
+    for n in cfg["sizes"]:
+        H1, H2 = inputs.chain_terms(n, cfg["J"], cfg["Delta"])
+        ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+        psi0 = inputs.random_states(1 << n, seed=cfg["psi_seed_base"] + n, batch=per)
+        fields = [inputs.cos_field(cfg["omega"], 1.0 + k / per) for k in range(per)]
+        fn = np.stack([nodes("CF4", fk, 0.0, tau, nsteps) for fk in fields])
+        psi = torch.from_numpy(psi0).cuda()
+        probs.append((ham, psi, fn))
+        host.append((n, H1, H2, psi0, fields, psi))
+    B.magnus_propagate_ragged(ctx, probs, B.CF4, tau, opts=B.leja_opts(tol_e))
+    torch.cuda.synchronize()
+    for n, H1, H2, psi0, fields, psi in host:
+        got = psi.cpu().numpy()
+        for k in (0, per - 1):
+            ref = mg.propagate("CF4", mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[k]), tau, nsteps, psi0[k],
+                               expm="taylor")
+            e = rel(got[k], ref)
+            say(f"ragged chain n={n} instance {k}, {nsteps} Cf4 steps: {e:.3e}")
+            assert e <= 50 * tol_e * 2 * nsteps
+    ctx.close()
+
+
+def test_chain_n20_lanczos_enclosures_more_steps():
+    """The benchmark's configuration (Lanczos enclosures, autotuned mapping):
+    6 Cf4 and 3 M4 steps of the n = 20 chain."""
+    cfg = inputs.CONFIGS["chain_n20"]
+    H1, H2 = inputs.chain_terms(20, cfg["J"], cfg["Delta"])
+    ctx = B.Context(max_dim=1 << 20)
+    ham = B.magnus_spectral_bounds_lanczos(ctx, B.DeviceHamiltonian.from_csr(H1, H2), steps=60, margin=0.01)
+    B.magnus_autotune(ctx, ham)
+    f = inputs.cos_field(cfg["omega"])
+    psi0 = inputs.random_states(1 << 20, seed=cfg["psi_seed"])
+    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), f)
+    for method, nsteps, nexp in (("CF4", 6, 2), ("M4", 3, 1)):
+        tol_e = cfg["budget_tol"] / (nexp * cfg["nsteps"])
+        psi = torch.from_numpy(psi0).cuda()
+        B.propagate(ctx, ham, B.METHODS[method], cfg["tau"], nodes(method, f, 0.0, cfg["tau"], nsteps), psi,
+                    opts=B.leja_opts(tol_e))
+        ref = mg.propagate(method, P, cfg["tau"], nsteps, psi0, expm="taylor")
+        e = rel(psi.cpu().numpy(), ref)
+        say(f"chain n=20 (Lanczos) {method} {nsteps} steps: {e:.3e}")
+        assert e <= 50 * tol_e * nexp * nsteps
+    ctx.close()
+
+
+@pytest.mark.parametrize("which", ["adjoint_chain_n16", "adjoint_dense_4096"])
+def test_adjoint_full_size_against_central_differences(which):
+    cfg = inputs.CONFIGS[which]
+    Pn, T, nsteps = cfg["params"], cfg["T"], cfg["nsteps"]
+    tau = T / nsteps
+    if "n" in cfg:
+        dim = 1 << cfg["n"]
+        H1, H2 = inputs.chain_terms(cfg["n"], cfg["J"], cfg["Delta"])
+        dh = B.DeviceHamiltonian.from_csr(H1, H2)
+    else:
+        dim = cfg["N"]
+        dh = B.DeviceHamiltonian.from_dense(inputs.powerlaw_hermitian(dim, cfg["alpha"], cfg["seeds"]["H0"]),
+                                            inputs.powerlaw_hermitian(dim, cfg["alpha"], cfg["seeds"]["V"]))
+    ctx = B.Context(max_dim=dim, max_batch=2)
+    ham = B.magnus_spectral_bounds(ctx, dh)
+    theta = inputs.fourier_theta(Pn, cfg["theta_seed"])
+    d0 = torch.from_numpy(inputs.random_states(dim, seed=cfg["psi_seed"])).cuda()
+    dt = torch.from_numpy(inputs.random_states(dim, seed=cfg["target_seed"])).cuda()
+    # early termination off: the a priori degrees make the loss smooth in theta
+    opts = B.leja_opts(cfg["budget_tol"] / (2 * nsteps), early_termination=False)
+    prob = A.ControlProblem.with_basis(ctx, ham, tau, nsteps, inputs.fourier_basis(Pn, T), d0, dt, every_k=20,
+                                       opts=opts)
+    loss, grad = prob.loss_and_grad(theta)
+
+    def dev_loss(th):
+        psi = d0.clone()
+        B.propagate(ctx, ham, B.CF4, tau, prob.basis_nodes @ th, psi, opts=opts)
+        return 1.0 - abs(complex(torch.vdot(dt, psi))) ** 2
+
+    assert abs(dev_loss(theta) - loss) <= 1e-12
+    eps = 1e-5
+    for k in (0, 1, 7, 15, 31):
+        e = np.zeros(Pn)
+        e[k] = eps
+        fd = (dev_loss(theta + e) - dev_loss(theta - e)) / (2 * eps)
+        say(f"{which}: theta_{k + 1}: grad {grad[k]:+.10e}, central difference {fd:+.10e}, |diff| {abs(fd - grad[k]):.2e}")
+        assert abs(fd - grad[k]) <= 1e-6
+    ctx.close()
