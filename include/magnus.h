@@ -286,6 +286,27 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
                    const void* psi_in, void* psi_out, int32_t batch, const magnus_leja_opts* opts,
                    magnus_stats* stats, magnus_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one Cf4 step
+ * of one state, as magnus_step_cf4 with batch = 1, without a context and
+ * without allocating.  Its workspace is a device array of the library of
+ * 16.8 MiB per device (eight vectors of up to 131072 = 2^17 entries, the norm
+ * partials, the CSR scan outputs and one control slot), set up on the first
+ * call on the current device and held until the process ends.
+ *   h             as magnus_step_cf4 (CSR or dense two-term terms, dim <= 2^17;
+ *                 dense terms run the two-term iteration, never assembled).
+ *   other args    as magnus_step_cf4; the call runs on the current device.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (the control slot is cleared at the start of each call):
+ * calls that overlap on one device, from several host threads or on several
+ * streams, race.  The first call with a given CSR term scans its structure
+ * (a stream sync), as the context entry points do once per term.
+ * Errors: ENOMEM (dim > 2^17), EHIP (no address for the array on this
+ * device), otherwise as magnus_step_cf4. */
+int magnus_step_cf4_noalloc(const magnus_hamiltonian* h, double tau, double f1, double f2,
+                            const void* psi_in, void* psi_out, const magnus_leja_opts* opts,
+                            magnus_stats* stats, magnus_stream stream);
+
 /* nsteps steps of `method` in place on psi (batch*dim complex128, device) on
  * the grid t_n = t0 + n tau (the one-step scheme of Section 2 repeated;
  * control flow stays on the host, Section 3).  Methods: MAGNUS_CF4, MAGNUS_M4,

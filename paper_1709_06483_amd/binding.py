@@ -67,7 +67,8 @@ EXPORTS = ("magnus_create", "magnus_destroy", "magnus_last_error", "magnus_check
            "magnus_timing", "magnus_timing_read", "magnus_reserve_dense", "magnus_adjoint_workspace_bytes",
            "magnus_propagate_adjoint", "magnus_propagate_ragged", "magnus_method_nodes",
            "magnus_dense_commutator", "magnus_dense_m6_prepare", "magnus_autotune",
-           "magnus_spectral_bounds_lanczos", "magnus_csr_commutator", "magnus_csr_m6_prepare")
+           "magnus_spectral_bounds_lanczos", "magnus_csr_commutator", "magnus_csr_m6_prepare",
+           "magnus_step_cf4_noalloc")
 KERNEL_PERSIST, KERNEL_CSR_LEJA3 = 6, 7
 KERNEL_CSR_LEJA, KERNEL_CSR_SPLIT, KERNEL_CSR_COMM, KERNEL_DENSE_LEJA, KERNEL_CSR_MULTI, KERNEL_DENSE_MFMA = 0, 1, 2, 3, 4, 5
 
@@ -91,6 +92,7 @@ def lib():
         "expmv_leja": (C.c_int, [vp, P(Hamiltonian), dbl, dbl, dbl, dbl, vp, vp, i32, P(LejaOpts), P(Stats), vp]),
         "magnus_step_cf4": (C.c_int, [vp, P(Hamiltonian), dbl, dbl, dbl, vp, vp, i32, P(LejaOpts), P(Stats), vp]),
         "magnus_step_m4": (C.c_int, [vp, P(Hamiltonian), dbl, dbl, dbl, vp, vp, i32, P(LejaOpts), P(Stats), vp]),
+        "magnus_step_cf4_noalloc": (C.c_int, [P(Hamiltonian), dbl, dbl, dbl, vp, vp, P(LejaOpts), P(Stats), vp]),
         "propagate": (C.c_int, [vp, P(Hamiltonian), i32, dbl, i64, P(dbl), i32, vp, i32, vp, i32, P(LejaOpts),
                                 P(Stats), vp]),
         "magnus_quadrature_nodes": (C.c_int, [i32, dbl, dbl, i64, P(dbl)]),
@@ -380,6 +382,19 @@ def magnus_step_cf4(ctx, ham, tau, f1, f2, psi_in, psi_out=None, opts=None, stat
 
 def magnus_step_m4(ctx, ham, tau, f1, f2, psi_in, psi_out=None, opts=None, stats=False):
     return _step(lib().magnus_step_m4, ctx, ham, tau, f1, f2, psi_in, psi_out, opts, stats)
+
+
+def magnus_step_cf4_noalloc(ham, tau, f1, f2, psi_in, psi_out, opts=None, stats=False):
+    """One Cf4 step of one state without a context: the library's device scratch
+    array is the workspace (dim <= 2^17).  psi_out is caller-allocated."""
+    if _states(psi_in, ham.dim) != 1 or _states(psi_out, ham.dim) != 1:
+        raise ValueError("the allocation-free step takes one state")
+    st = Stats()
+    o = opts or leja_opts()
+    rc = lib().magnus_step_cf4_noalloc(C.byref(ham.struct), tau, f1, f2, _ptr(psi_in), _ptr(psi_out), C.byref(o),
+                                       C.byref(st) if stats else None, _stream())
+    s = _finish(rc, st, stats)
+    return (psi_out, s) if stats else psi_out
 
 
 def propagate(ctx: Context, ham: DeviceHamiltonian, method: int, tau: float, f_nodes, psi, checkpoints=None,

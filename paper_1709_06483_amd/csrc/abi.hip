@@ -1077,6 +1077,70 @@ int check_batch(magnus_ctx* ctx, int32_t batch) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free Cf4 step (magnus_step_cf4_noalloc): the eight
+// workspace vectors of one state of up to kNoAllocMaxDim entries, the
+// per-workgroup norm partials of the iteration kernels, the outputs of the
+// CSR structure scan and one control slot.  A file-scope device array, so the
+// code object's loader places it on every device the library runs on, and it
+// stays there until the process ends.  Host code never uses the array's name
+// as an address: it asks each device for its copy's address once
+// (hipGetSymbolAddress) and passes that pointer on.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNoAllocMaxDim = 1 << 17;
+constexpr size_t kNaAlign = 256;
+constexpr size_t na_round(size_t b) { return (b + kNaAlign - 1) / kNaAlign * kNaAlign; }
+constexpr size_t kNaVecBytes = (size_t)kNumVec * (size_t)kNoAllocMaxDim * sizeof(double2);
+constexpr int64_t kNaGrid = kNoAllocMaxDim / 8 + 2;  // as magnus_create: 8 rows per smallest row block
+constexpr size_t kNaPartials = 2 * (size_t)kNaGrid + 64;
+constexpr int64_t kNaScanLen = 2 * (kNoAllocMaxDim / 4 + 2) + 3 * (kNoAllocMaxDim / 256 + 2);
+constexpr size_t kNaPartialOff = kNaVecBytes;
+constexpr size_t kNaScanOff = kNaPartialOff + na_round(kNaPartials * sizeof(double));
+constexpr size_t kNaSlotOff = kNaScanOff + na_round((size_t)kNaScanLen * sizeof(double));
+constexpr size_t kNoAllocBytes = kNaSlotOff + na_round(sizeof(Slot));  // 16.8 MiB
+constexpr int kNaMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_na_mu;
+// One context per device whose workspace points into that device's scratch
+// (set up on the first call on the device; never freed).
+magnus_ctx g_na_ctx[kNaMaxDevices];
+
+int noalloc_context(magnus_ctx** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNaMaxDevices) return fail(MAGNUS_EINVAL, "device %d beyond the %d the library serves", dev, kNaMaxDevices);
+  std::lock_guard<std::mutex> g(g_na_mu);
+  magnus_ctx& c = g_na_ctx[dev];
+  if (!c.vecs) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MAGNUS_EHIP, "address of the scratch array on device %d: %s", dev, hipGetErrorString(e));
+    unsigned char* base = static_cast<unsigned char*>(ptr);
+    c.device = dev;
+    c.max_dim = kNoAllocMaxDim;
+    c.max_batch = 1;
+    c.max_grid = kNaGrid;
+    c.partials = reinterpret_cast<double*>(base + kNaPartialOff);
+    c.npartials = kNaPartials;
+    c.scan = reinterpret_cast<double*>(base + kNaScanOff);
+    c.scan_len = kNaScanLen;
+    c.slots = reinterpret_cast<Slot*>(base + kNaSlotOff);
+    c.nslots = 1;
+    c.persist = 0;
+    if (const char* v = getenv("MAGNUS_CSR_VARIANT")) c.csr_variant = atoi(v);
+    c.vecs = reinterpret_cast<double2*>(base);  // last: marks the device's context ready
+  }
+  *out = &c;
+  return MAGNUS_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* magnus_last_error(void) { return g_err.c_str(); }
@@ -1701,6 +1765,18 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
                    const void* psi_in, void* psi_out, int32_t batch, const magnus_leja_opts* opts,
                    magnus_stats* stats, magnus_stream stream) {
   return step_common(MAGNUS_M4, ctx, h, tau, f1, f2, psi_in, psi_out, batch, opts, stats, stream);
+}
+
+int magnus_step_cf4_noalloc(const magnus_hamiltonian* h, double tau, double f1, double f2, const void* psi_in,
+                            void* psi_out, const magnus_leja_opts* opts, magnus_stats* stats, magnus_stream stream) {
+  if (!h) return fail(MAGNUS_EINVAL, "null hamiltonian");
+  if (h->H1.dim > kNoAllocMaxDim)
+    return fail(MAGNUS_ENOMEM, "dim %lld exceeds the %lld entries the allocation-free scratch holds",
+                (long long)h->H1.dim, (long long)kNoAllocMaxDim);
+  magnus_ctx* ctx = nullptr;
+  int rc = noalloc_context(&ctx);
+  if (rc) return rc;
+  return step_common(MAGNUS_CF4, ctx, h, tau, f1, f2, psi_in, psi_out, 1, opts, stats, stream);
 }
 
 int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, double tau, int64_t nsteps,
