@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--workload", default="chain_n20",
                     choices=["chain_n20", "chain_n10", "dense_8192", "batched_dense_4096", "ragged_chains",
                              "adjoint_chain_n16", "adjoint_dense_4096", "accuracy_cost_dense",
-                             "accuracy_cost_sparse", "chain_sizes", "m6_chains"],
+                             "accuracy_cost_sparse", "chain_sizes", "m6_chains", "multi_chain"],
                     help="chain_n20 is the headline line; the others print one informational line each")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size heuristic for the CSR kernel")
     ap.add_argument("--timing-stride", type=int, default=7,
@@ -71,6 +71,8 @@ def main():
                     help="skip the compact batched, ragged and adjoint measurements appended to the line")
     ap.add_argument("--bounds", choices=["gershgorin", "lanczos"], default="lanczos",
                     help="spectral enclosures of the terms: rigorous Gershgorin discs or Lanczos estimates")
+    ap.add_argument("--chain-n", type=int, default=18, help="multi_chain: spins of the chain")
+    ap.add_argument("--batch", type=int, default=16, help="multi_chain: states propagated together")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -462,7 +464,8 @@ def other_workload(name: str, args, emit: bool = True):
     elif name == "ragged_chains":
         cfg = inputs.CONFIGS["ragged_chains"]
         tau, sizes, per = cfg["tau"], cfg["sizes"], cfg["per_size"]
-        ctx = B.Context(max_dim=1 << max(sizes), max_batch=per)
+        # a workspace holding every large problem at once, so they advance together
+        ctx = B.Context(max_dim=max(1 << max(sizes), sum(1 << n for n in sizes if (1 << n) > 4096)), max_batch=per)
         probs = []
         for n in sizes:
             H1, H2 = inputs.chain_terms(n, cfg["J"], cfg["Delta"])
@@ -569,6 +572,30 @@ def other_workload(name: str, args, emit: bool = True):
         line.update({"metric": "M6 Magnus steps/sec on CSR terms, chains n = 16 and 20 (1e-13 per exponential)",
                      "value": per_n["20"]["steps_per_s"], "unit": "steps/s (n = 20)", "steps": K,
                      "per_n": per_n})
+    elif name == "multi_chain":
+        # one group of states on one chain (the multi-state CSR iteration of ragged
+        # batches and batched calls): Cf4 with per-state field amplitudes 1 + k/B
+        n, Bn, tau = args.chain_n, args.batch, 0.01
+        dim = 1 << n
+        H1, H2 = inputs.chain_terms(n)
+        ctx = B.Context(max_dim=dim, max_batch=Bn)
+        ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+        psi = torch.from_numpy(inputs.random_states(dim, seed=300 + n, batch=Bn)).cuda()
+        t = B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K)
+        fn = np.stack([np.vectorize(inputs.cos_field(2.0, 1.0 + k / Bn))(t) for k in range(Bn)])
+        tol_e = 1e-10 / (2 * 100)
+        B.propagate(ctx, ham, B.CF4, tau, fn[:, :W], psi, opts=B.leja_opts(tol_e))
+        ctx.timing(True)
+        ms, (_, st) = _timed(lambda: B.propagate(ctx, ham, B.CF4, tau, fn[:, W:], psi, opts=B.leja_opts(tol_e),
+                                                  stats=True))
+        kms, kn = ctx.timing_read(B.KERNEL_CSR_MULTI)
+        ctx.timing(False)
+        it_bytes = 20 * (H1.nnz + H2.nnz) + 8 * (dim + 1) + 64 * dim * Bn
+        line.update({"metric": f"multi-state Cf4 steps/sec, chain n={n}, {Bn} states per CSR pass",
+                     "value": K / (ms * 1e-3), "unit": "steps/s", "steps": K, "ms_per_step": ms / K,
+                     "kernel_avg_us": 1e3 * kms / max(kn, 1), "kernel_launches": kn,
+                     "bytes_per_iteration": it_bytes,
+                     "kernel_gbps": it_bytes / max(kms / max(kn, 1) * 1e-3, 1e-12) / 1e9})
     elif name in ("accuracy_cost_dense", "accuracy_cost_sparse"):
         # Figures 4 and 8 of Section 4 on this GPU: N = 2^12, error at t = 1 against an
         # M6 reference, each run with the Leja tolerance set to a tenth of the error it

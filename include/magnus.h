@@ -30,6 +30,20 @@
  * - Return value: MAGNUS_OK (0) or a negative status; magnus_last_error()
  *   returns a thread-local message describing the last failure.
  * - Precision: all arithmetic is FP64 (device and host).
+ * - Device memory is allocated by magnus_create (the workspace) and, on
+ *   request only, by the preparation calls that build matrices the hot path
+ *   then reuses (magnus_reserve_dense, magnus_dense_commutator,
+ *   magnus_csr_commutator, magnus_dense_m6_prepare, magnus_csr_m6_prepare):
+ *   their sizes depend on the terms (dim^2 per dense matrix, the commutator's
+ *   nonzeros), which a context created for a dimension cannot know.  Every
+ *   other call allocates nothing on the device; magnus_step_cf4_noalloc needs
+ *   no context at all.
+ * - Dense terms are row-major (each row contiguous, stride ld): the GEMV and
+ *   GEMM kernels stream rows, and a Hermitian term's column-major layout is
+ *   its conjugate's row-major one.
+ * - Spectral enclosures come from magnus_spectral_bounds (rigorous
+ *   Gershgorin discs) or magnus_spectral_bounds_lanczos (Lanczos estimates,
+ *   with a step count); one entry point per method.
  */
 #ifndef MAGNUS_H
 #define MAGNUS_H
@@ -290,7 +304,7 @@ int magnus_step_m4(magnus_ctx* ctx, const magnus_hamiltonian* h, double tau, dou
  * capture, tight serving loops, harnesses that forbid hipMalloc): one Cf4 step
  * of one state, as magnus_step_cf4 with batch = 1, without a context and
  * without allocating.  Its workspace is a device array of the library of
- * 16.8 MiB per device (eight vectors of up to 131072 = 2^17 entries, the norm
+ * 17.0 MiB per device (eight vectors of up to 131072 = 2^17 entries, the norm
  * partials, the CSR scan outputs and one control slot), set up on the first
  * call on the current device and held until the process ends.
  *   h             as magnus_step_cf4 (CSR or dense two-term terms, dim <= 2^17;
@@ -347,11 +361,19 @@ typedef struct {
  * product-of-exponentials methods (Cf4, Cf4:3, M2) run in persistent launches
  * (one workgroup per state carries every step with its vectors in LDS; up to
  * 256 or max_batch states per launch) when their dimension is at most 4096
- * (none with MAGNUS_PERSIST=0);
- * the others run first, as batched propagations, each followed by a host
- * wait that reports a non-finite norm (ENAN) at once.  Tolerances as in
- * propagate (tol_mode 1: budget over the exponentials of each state).
- * Errors as propagate. */
+ * (none with MAGNUS_PERSIST=0).  The larger CSR problems advance together
+ * when there are at least 2 of them, all with the same batch, split into
+ * groups of G states (G the group size magnus_autotune chose for the largest
+ * of them, else the largest of 32, 16, 8, 4, 2 within the batch, halved until
+ * it divides the batch; at most 8 groups), their states fit the context's
+ * workspace at once (sum of dim * batch at most max_dim * max_batch) and
+ * their control slots fit beside the small states': one launch per Leja
+ * iteration serves every group (each problem with its own degree,
+ * coefficients and stop tests), then one launch makes all their columns'
+ * stop decisions; no host wait.  Otherwise they run first, as
+ * batched propagations, each followed by a host wait that reports a
+ * non-finite norm (ENAN) at once.  Tolerances as in propagate (tol_mode 1:
+ * budget over the exponentials of each state).  Errors as propagate. */
 int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_t nprob, int32_t method,
                             double tau, int64_t nsteps, const magnus_leja_opts* opts, magnus_stats* stats,
                             magnus_stream stream);
@@ -404,7 +426,15 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
  *   variant, group       HOST out (may be NULL): the chosen code and group size
  *   variant_us[7], group_us[5]  HOST out (may be NULL): measured microseconds per
  *                        launch (group entries NAN where not tried).
- * CSR terms only.  Synchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+ * Dense terms: times the two-term GEMV iteration with 1, 2 and 4 rows per
+ * wave and, when batch > 1, the FP64-MFMA group iteration of batch states
+ * with each tile shape (0: 32 rows x 64 states with K split between two
+ * groups of four waves, 1: 32 x 64, 2: 64 x 64, 3: 64 x 64 with K split,
+ * 4: 32 x 128 with K split; one term when the context holds an assembly
+ * buffer, else two), and keeps the fastest for these terms (H1's values and
+ * dim); then variant receives the rows per wave, group the tile code,
+ * variant_us[0..2] and group_us[0..4] the timings.
+ * Synchronous.  Errors: EINVAL, ENOMEM, EHIP. */
 int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch, int32_t* variant,
                     int32_t* group, double* variant_us, double* group_us, magnus_stream stream);
 

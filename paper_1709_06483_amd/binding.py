@@ -302,14 +302,27 @@ CSR_VARIANTS = {1: "nonzero streaming", 2: "row per lane, 64 rows", 3: "row per 
                 7: "streamed wave tiles"}
 
 
+DENSE_ROWS_PER_WAVE = (1, 2, 4)
+MFMA_TILES = {0: "32x64, K split in two", 1: "32x64", 2: "64x64", 3: "64x64, K split in two",
+              4: "32x128, K split in two"}
+
+
 def magnus_autotune(ctx: Context, ham: DeviceHamiltonian, batch: int = 1) -> dict:
-    """Time the CSR kernel variants (and multi-state group sizes when batch > 1) on these
-    terms and keep the fastest in the context.  Returns the choices and the timings."""
+    """Time the kernel variants on these terms and keep the fastest in the context.
+    CSR terms: the row mappings of the single-state iteration (and multi-state group
+    sizes when batch > 1).  Dense terms: rows per wave of the GEMV iteration (and the
+    FP64-MFMA tile shapes of group iterations of `batch` states).  Returns the choices
+    and the timings."""
     v, g = C.c_int32(), C.c_int32()
     vus = np.zeros(len(CSR_VARIANTS))
     gus = np.zeros(5)
     _check(lib().magnus_autotune(ctx.handle, C.byref(ham.struct), batch, C.byref(v), C.byref(g), _dptr(vus),
                                  _dptr(gus), _stream()))
+    if ham.struct.H1.format == DENSE:
+        return {"rows_per_wave": int(v.value), "mfma_tile": int(g.value) if batch > 1 else None,
+                "mfma_tile_name": MFMA_TILES[int(g.value)] if batch > 1 else None,
+                "rows_per_wave_us": {str(r): float(vus[k]) for k, r in enumerate(DENSE_ROWS_PER_WAVE)},
+                "mfma_tile_us": {MFMA_TILES[t]: (None if np.isnan(gus[t]) else float(gus[t])) for t in MFMA_TILES}}
     return {"variant": int(v.value), "variant_name": CSR_VARIANTS[int(v.value)], "group": int(g.value),
             "variant_us": {CSR_VARIANTS[k + 1]: float(vus[k]) for k in range(len(CSR_VARIANTS))},
             "group_us": {str(b): (None if np.isnan(gus[i]) else float(gus[i])) for i, b in enumerate((2, 4, 8, 16, 32))}}

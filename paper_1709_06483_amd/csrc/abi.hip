@@ -78,6 +78,21 @@ struct magnus_ctx {
   ColParam* table = nullptr;   // kTableCap entries
   unsigned char* arena = nullptr;  // kArenaBytes
   int persist = 1;  // MAGNUS_PERSIST: 0 never, 1 by size and state count, 2 every state of at most kSmallDim
+  int fuse = 1;     // MAGNUS_FUSE: 0 a decide kernel after every iteration, 1 stop tests fused on small grids
+  magnus::IterArgs fz_last{};  // the arguments of a final check of the last fused iteration
+  bool fz_pending = false;     // a fused iteration ran since the last final check
+  // graph replay of single-state steps (MAGNUS_GRAPH: 0 off, 1 on): one Magnus
+  // step captured on cap_stream, replayed once per step with the step's Leja
+  // coefficients read from a device table indexed by the counter *gctr
+  int graph = 0;         // off by default: replays measured slower than launches once the stop tests are fused
+  int graph_chunk = 0;  // MAGNUS_GRAPH_STEPS: steps per uploaded table chunk (0: as many as fit)
+  int ragged_joint = 1; // MAGNUS_RAGGED_JOINT: 0 runs a ragged batch's large problems one after another
+  int* gctr = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph_g = nullptr;
+  hipGraphExec_t graph_x = nullptr;
+  hipEvent_t graph_done = nullptr;  // recorded after the last replay of the current graph
+  std::vector<magnus::IterCoef> graph_table;  // host side of the last uploaded table chunk
   double2* assembled = nullptr;  // magnus_reserve_dense
   int64_t assembled_dim = 0;
   double2* comm = nullptr;       // magnus_dense_commutator: K = i[H1, H2], row stride comm_dim
@@ -123,6 +138,11 @@ struct magnus_ctx {
   // magnus_autotune results, per CSR term pair (H1 row_ptr, dim): the variant code
   // of the single-state iteration and the states per multi-state pass
   std::map<std::pair<const void*, int64_t>, int> tuned_variant, tuned_group;
+  // magnus_autotune results for dense terms, per (H1 values, dim): rows per
+  // wave of the GEMV iteration and the FP64-MFMA tile of group iterations
+  std::map<std::pair<const void*, int64_t>, int> tuned_dense_rpw, tuned_mfma;
+  int dense_rpw_env = 0;   // MAGNUS_DENSE_RPW: 1, 2 or 4 rows per wave of the GEMV iteration (0: tuned or 2)
+  int mfma_tile_env = -1;  // MAGNUS_MFMA_TILE: 0..4 forces an FP64-MFMA tile shape (-1: tuned or 0)
   int timing = 0;  // 0 off, k >= 1: every k-th launch of each kernel class is bracketed
   int64_t timing_seq[MAGNUS_KERNEL_CSR_LEJA3 + 1] = {};  // launches of each class since enabling
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;
@@ -308,6 +328,18 @@ int rows_per_block(magnus_ctx* ctx, const magnus_hamiltonian* h) {
   return variant_rows(it == ctx->tuned_variant.end() ? 0 : it->second, h->H1.dim);
 }
 
+// Tuned dense choices (the defaults until magnus_autotune ran on these terms).
+int dense_rpw(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  if (ctx->dense_rpw_env > 0) return ctx->dense_rpw_env;
+  auto it = ctx->tuned_dense_rpw.find({h->H1.val, h->H1.dim});
+  return it == ctx->tuned_dense_rpw.end() ? 2 : it->second;
+}
+int mfma_tile(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
+  if (ctx->mfma_tile_env >= 0) return ctx->mfma_tile_env;
+  auto it = ctx->tuned_mfma.find({h->H1.val, h->H1.dim});
+  return it == ctx->tuned_mfma.end() ? 0 : it->second;
+}
+
 hipEvent_t next_event(magnus_ctx* ctx) {
   if (ctx->pool_used == ctx->pool.size()) {
     hipEvent_t e;
@@ -331,6 +363,16 @@ hipError_t timed(magnus_ctx* ctx, int kind, hipStream_t s, F f) {
   return e;
 }
 
+// The last fused iteration's partials are checked for non-finite norms by a
+// small kernel, enqueued before anything else writes the partials buffer or
+// the control slots (another kind of launch, the end of the call).
+int flush_fused_check(magnus_ctx* ctx, hipStream_t s) {
+  if (!ctx->fz_pending) return MAGNUS_OK;
+  ctx->fz_pending = false;
+  HIP_TRY(magnus::launch_leja_final_check(ctx->fz_last, s));
+  return MAGNUS_OK;
+}
+
 // Launch one Leja iteration (both passes for a commutator exponent).
 // One Leja iteration of Method M6 on CSR terms, the exponent's nested
 // commutators applied to vectors.  With K = i[H1,H2], P_a = -i[H_a,K] assembled
@@ -346,6 +388,7 @@ hipError_t timed(magnus_ctx* ctx, int kind, hipStream_t s, F f) {
 // applies them and makes the Leja update, then the stop decision (ten matrix
 // reads where the thirteen products one by one would make thirteen).
 int m6_csr_iteration(magnus_ctx* ctx, const ExpOp& op, double scale, const IterArgs& a, hipStream_t s) {
+  if (int rc = flush_fused_check(ctx, s)) return rc;
   const magnus_hamiltonian* h = op.h;
   const int dim = (int)h->H1.dim;
   const double* c = op.m6c;
@@ -366,12 +409,47 @@ int m6_csr_iteration(magnus_ctx* ctx, const ExpOp& op, double scale, const IterA
   return MAGNUS_OK;
 }
 
+// Stop test of iteration i: fused into the iteration kernel on grids of at
+// most kFuseMaxGrid workgroups (every workgroup reduces iteration i-1's
+// partials, which alternate between two halves of the partials buffer),
+// else a decide kernel after each iteration.  Sets a->fused.
+int setup_stop_test(magnus_ctx* ctx, const ExpPlan& P, int i, int grid, IterArgs* a, hipStream_t s) {
+  a->iter = i;
+  a->fused = 0;
+  if (!ctx->fuse || grid > magnus::kFuseMaxGrid) return flush_fused_check(ctx, s);
+  const size_t half = 2 * (size_t)ctx->max_grid;
+  a->fused = 1;
+  a->partials = ctx->partials + (size_t)(i & 1) * half;
+  a->prev_partials = ctx->partials + (size_t)((i - 1) & 1) * half;
+  a->prev_grid = grid;
+  a->prev_dabs = i >= 2 ? std::abs(P.d[i - 1]) : 0.0;
+  // the call's last fused iteration is checked for non-finite norms at its end
+  ctx->fz_last = *a;
+  ctx->fz_last.iter = i + 1;
+  ctx->fz_last.prev_partials = a->partials;
+  ctx->fz_pending = true;
+  return MAGNUS_OK;
+}
+
+// Table column of one iteration launch in a captured step (graph replay).
+struct TableRef {
+  const magnus::IterCoef* col;  // record of this iteration in step 0
+  int stride;                   // records per step
+  const int* step;              // device step counter
+};
+
 int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, const double2* win,
-                     double2* wout, double2* pacc, double tol_sub, int early, hipStream_t s) {
+                     double2* wout, double2* pacc, double tol_sub, int early, hipStream_t s,
+                     const TableRef* tab = nullptr) {
   const magnus_hamiltonian* h = op.h;
   const int dim = (int)h->H1.dim;
   const auto& xi = magnus::leja_points();
   IterArgs a{};
+  if (tab) {
+    a.coef = tab->col;
+    a.coef_stride = tab->stride;
+    a.step = tab->step;
+  }
   a.slot = ctx->slots;
   a.partials = ctx->partials;
   a.a1 = P.scale * op.a;
@@ -386,6 +464,7 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
   a.early = early;
   a.first = (i == 1);
   a.check_stop = (i != 1);
+  a.iter = i;
   a.wcur = win;
   a.wout = wout;
   a.pacc = pacc;
@@ -394,12 +473,16 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
     if (op.kappa != 0.0) return fail(MAGNUS_EINVAL, "dense commutator exponents run assembled");
     a.x1 = win;
     a.x2 = win;
+    const int rpw = dense_rpw(ctx, h);
+    const int grid = magnus::dense2_grid(dim, op.assembled ? 1 : 2, rpw);
+    if (int rc = setup_stop_test(ctx, P, i, grid, &a, s)) return rc;
+    const bool fused = a.fused;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_LEJA, s, [&] {
-      if (op.assembled) return magnus::launch_dense2_iter(op.assembled, nullptr, dim, dim, a, s);
+      if (op.assembled) return magnus::launch_dense2_iter(op.assembled, nullptr, dim, dim, a, s, rpw);
       return magnus::launch_dense2_iter(reinterpret_cast<const double2*>(h->H1.val),
-                                        reinterpret_cast<const double2*>(h->H2.val), dim, h->H1.ld, a, s);
+                                        reinterpret_cast<const double2*>(h->H2.val), dim, h->H1.ld, a, s, rpw);
     }));
-    HIP_TRY(magnus::launch_leja_decide(a, magnus::dense2_grid(dim, op.assembled ? 1 : 2), s));
+    if (!fused) HIP_TRY(magnus::launch_leja_decide(a, grid, s));
     return MAGNUS_OK;
   }
   CsrDev t1{h->H1.row_ptr, h->H1.col_idx, reinterpret_cast<const double2*>(h->H1.val)};
@@ -408,9 +491,12 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
   if (op.kappa == 0.0) {
     a.x1 = win;
     a.x2 = win;
+    const int grid = magnus::csr2_grid(dim, rpb);
+    if (int rc = setup_stop_test(ctx, P, i, grid, &a, s)) return rc;
+    const bool fused = a.fused;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA, s,
                   [&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }));
-    HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
+    if (!fused) HIP_TRY(magnus::launch_leja_decide(a, grid, s));
     return MAGNUS_OK;
   }
   if (csr_comm_ready(ctx, h)) {
@@ -418,45 +504,83 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
     CsrDev t3{ctx->kc_rp, ctx->kc_ci, ctx->kc_val};
     a.x1 = win;
     a.x2 = win;
+    const int grid = magnus::csr3_grid(dim);
+    if (int rc = setup_stop_test(ctx, P, i, grid, &a, s)) return rc;
+    const bool fused = a.fused;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA3, s,
                   [&] { return magnus::launch_csr3_iter(t1, t2, t3, dim, a, P.scale * op.kappa, s); }));
-    HIP_TRY(magnus::launch_leja_decide(a, magnus::csr3_grid(dim), s));
+    if (!fused) HIP_TRY(magnus::launch_leja_decide(a, grid, s));
     return MAGNUS_OK;
   }
+  // Commutator exponents take two passes per iteration.  The first pass
+  // makes the stop test (fused or not); with the fused test the second pass
+  // only reads the verdict the first one recorded, and it writes the
+  // partials the next iteration's first pass reduces.
   double2* U = ctx->vec(kU);
   double2* V = ctx->vec(kV);
+  const int grid = magnus::csr2_grid(dim, rpb);
+  if (int rc = setup_stop_test(ctx, P, i, grid, &a, s)) return rc;
+  const bool fused = a.fused;
+  IterArgs p1 = a;
+  p1.x1 = win;
+  p1.x2 = win;
+  p1.wout = U;
+  p1.pacc = V;
+  if (fused) {
+    a.fused = 0;
+    a.check_stop = 1;
+  }
   if (rpb == magnus::kStreamTile) {
     // streamed commutator: pass 1 writes U = a1 w + i k H2 w and V = a2 w - i k H1 w,
     // pass 2 is the two-term iteration on H1 U + H2 V
-    IterArgs p1 = a;
-    p1.x1 = win;
-    p1.x2 = win;
-    p1.wout = U;
-    p1.pacc = V;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_SPLIT, s,
                   [&] { return magnus::launch_csr2_iter(magnus::kSplitComm, t1, t2, dim, p1, rpb, s); }));
     a.x1 = U;
     a.x2 = V;
     a.a1 = 1.0;
     a.a2 = 1.0;
+    a.unit_a = 1;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_COMM, s,
                   [&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }));
-    HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
+    if (!fused) HIP_TRY(magnus::launch_leja_decide(a, grid, s));
     return MAGNUS_OK;
   }
   // commutator: pass 1 writes U = H1 w, V = H2 w; pass 2 applies H1 V and H2 U
-  IterArgs p1 = a;
-  p1.x1 = win;
-  p1.x2 = win;
-  p1.wout = U;
-  p1.pacc = V;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_SPLIT, s,
                 [&] { return magnus::launch_csr2_iter(magnus::kSplit, t1, t2, dim, p1, rpb, s); }));
   a.x1 = V;
   a.x2 = U;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_COMM, s,
                 [&] { return magnus::launch_csr2_iter(magnus::kLejaComm, t1, t2, dim, a, rpb, s); }));
-  HIP_TRY(magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s));
+  if (!fused) HIP_TRY(magnus::launch_leja_decide(a, grid, s));
+  return MAGNUS_OK;
+}
+
+// The launches of one planned exponential: P.lp.s substeps of P.lp.m
+// iterations, the Newton sums in kS0/kS1 (or dst), w in kA/kB.  With a table
+// (capture of a replayed step) iteration i of substep sub reads record
+// tab->col + sub * m + i - 1 of the step.
+int enqueue_exponential(magnus_ctx* ctx, const ExpOp& it, const ExpPlan& P, const double2* src, double2* dst,
+                        double tol_sub, int early, const TableRef* tab, hipStream_t s) {
+  const int64_t dim = it.h->H1.dim;
+  const int m = P.lp.m, ns = P.lp.s;
+  const double2* cur = src;
+  for (int sub = 0; sub < ns; ++sub) {
+    const bool last = (sub == ns - 1);
+    double2* Pbuf;
+    if (last && dst != cur) Pbuf = dst;
+    else Pbuf = (cur == ctx->vec(kS0)) ? ctx->vec(kS1) : ctx->vec(kS0);
+    for (int i = 1; i <= m; ++i) {
+      const double2* win = (i == 1) ? cur : ((i - 1) % 2 == 1 ? ctx->vec(kA) : ctx->vec(kB));
+      double2* wout = (i % 2 == 1) ? ctx->vec(kA) : ctx->vec(kB);
+      TableRef t{};
+      if (tab) t = TableRef{tab->col + (size_t)sub * m + (i - 1), tab->stride, tab->step};
+      int rc = launch_iteration(ctx, it, P, i, win, wout, Pbuf, tol_sub, early, s, tab ? &t : nullptr);
+      if (rc) return rc;
+    }
+    cur = Pbuf;
+  }
+  if (cur != dst) HIP_TRY(magnus::launch_copy(cur, dst, dim, s));
   return MAGNUS_OK;
 }
 
@@ -495,21 +619,8 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
                                           ctx->assembled, s));
     it = ExpOp{op.h, 1.0, 0.0, 0.0, ctx->assembled};
   }
-  const double2* cur = src;
-  for (int sub = 0; sub < ns; ++sub) {
-    const bool last = (sub == ns - 1);
-    double2* Pbuf;
-    if (last && dst != cur) Pbuf = dst;
-    else Pbuf = (cur == ctx->vec(kS0)) ? ctx->vec(kS1) : ctx->vec(kS0);
-    for (int i = 1; i <= m; ++i) {
-      const double2* win = (i == 1) ? cur : ((i - 1) % 2 == 1 ? ctx->vec(kA) : ctx->vec(kB));
-      double2* wout = (i % 2 == 1) ? ctx->vec(kA) : ctx->vec(kB);
-      int rc = launch_iteration(ctx, it, P, i, win, wout, Pbuf, tol_sub, o->early_termination, s);
-      if (rc) return rc;
-    }
-    cur = Pbuf;
-  }
-  if (cur != dst) HIP_TRY(magnus::launch_copy(cur, dst, dim, s));
+  int rc = enqueue_exponential(ctx, it, P, src, dst, tol_sub, o->early_termination, nullptr, s);
+  if (rc) return rc;
   acc->exponentials += 1;
   acc->substeps += ns;
   acc->planned += (int64_t)m * ns;
@@ -522,6 +633,7 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
 int begin_call(magnus_ctx* ctx, hipStream_t s) {
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->sticky_status = 0;
+  ctx->fz_pending = false;
   HIP_TRY(magnus::launch_slot_reset(ctx->slots, ctx->nslots, s));
   return MAGNUS_OK;
 }
@@ -541,6 +653,7 @@ int read_slots(magnus_ctx* ctx, hipStream_t s, long long* iters, int* status) {
 }
 
 int end_call(magnus_ctx* ctx, const Acc& acc, double tol_e, magnus_stats* st, hipStream_t s) {
+  if (int rc = flush_fused_check(ctx, s)) return rc;
   if (!st) return MAGNUS_OK;
   long long iters = 0;
   int status = 0;
@@ -771,6 +884,7 @@ int upload_table(magnus_ctx* ctx, const std::vector<ColParam>& table, hipStream_
 // Launch the iterations of one planned multi-state exponential.
 int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E, double tol_e, int early,
                  hipStream_t s) {
+  if (int rc = flush_fused_check(ctx, s)) return rc;
   const int dim = (int)h->H1.dim;
   const int B = E.B;
   const size_t n = (size_t)dim * B;
@@ -816,7 +930,7 @@ int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E
                       [&] { return magnus::launch_dense_frechet(D1, D2, dim, h->H1.ld, a, s); }));
       else if (dense)
         HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_MFMA, s,
-                      [&] { return magnus::launch_dense_mfma(E.dense_terms, D1, D2, ldd, dim, a, s); }));
+                      [&] { return magnus::launch_dense_mfma(E.dense_terms, D1, D2, ldd, dim, a, s, mfma_tile(ctx, h)); }));
       else
         HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_MULTI, s, [&] { return magnus::launch_csr2_multi(mode, t1, t2, dim, a, s); }));
       HIP_TRY(magnus::launch_multi_decide(a, grid, s));
@@ -930,6 +1044,129 @@ int multi_cf_steps(magnus_ctx* ctx, const magnus_hamiltonian* h, const magnus::S
 }
 
 // ---------------------------------------------------------------------------
+// Ragged batches: the large problems of equal group size B advance together,
+// one launch per Leja iteration serving every problem (and one decision
+// launch for all their columns), each problem with its own terms, degrees,
+// workspace slice, control slots and partial sums.
+// ---------------------------------------------------------------------------
+struct RagProblem {
+  const magnus_problem* P;
+  int c0;         // first of its states in the problem (a group of B states)
+  size_t voff;    // offset of its slice inside every workspace vector
+  int slot0;      // its first control slot
+  size_t poff;    // offset of its partial sums
+  double2* v(magnus_ctx* ctx, int k) const { return ctx->vec(k) + voff; }
+  double2* psi() const { return reinterpret_cast<double2*>(P->psi) + (size_t)c0 * P->h.H1.dim; }
+};
+
+// One exponential of every problem (E[q] planned for problem q).
+int launch_ragged_exp(magnus_ctx* ctx, const std::vector<RagProblem>& R, const std::vector<MultiExp>& E, int B,
+                      double tol_e, int early, hipStream_t s) {
+  if (int rc = flush_fused_check(ctx, s)) return rc;
+  const size_t np = R.size();
+  std::vector<const double2*> cur(np);
+  std::vector<double2*> pbuf(np);
+  int max_s = 1;
+  for (size_t q = 0; q < np; ++q) {
+    cur[q] = E[q].src;
+    max_s = std::max(max_s, E[q].s);
+  }
+  for (int sub = 0; sub < max_s; ++sub) {
+    int max_m = 0;
+    for (size_t q = 0; q < np; ++q) {
+      if (sub >= E[q].s) continue;
+      const bool last = sub == E[q].s - 1;
+      if (last && E[q].dst != cur[q]) pbuf[q] = E[q].dst;
+      else pbuf[q] = cur[q] == R[q].v(ctx, kS0) ? R[q].v(ctx, kS1) : R[q].v(ctx, kS0);
+      max_m = std::max(max_m, E[q].m);
+    }
+    for (int i = 1; i <= max_m; ++i) {
+      magnus::RaggedArgs r{};
+      for (size_t q = 0; q < np; ++q) {
+        if (sub >= E[q].s || i > E[q].m) continue;
+        const magnus_hamiltonian& h = R[q].P->h;
+        magnus::RaggedProblem& rp = r.p[r.np++];
+        rp.t1 = CsrDev{h.H1.row_ptr, h.H1.col_idx, reinterpret_cast<const double2*>(h.H1.val)};
+        rp.t2 = CsrDev{h.H2.row_ptr, h.H2.col_idx, reinterpret_cast<const double2*>(h.H2.val)};
+        rp.dim = (int)h.H1.dim;
+        MultiArgs& a = rp.a;
+        a.x = (i == 1) ? cur[q] : ((i - 1) % 2 == 1 ? R[q].v(ctx, kA) : R[q].v(ctx, kB));
+        a.wout = (i % 2 == 1) ? R[q].v(ctx, kA) : R[q].v(ctx, kB);
+        a.pacc = pbuf[q];
+        a.slots = ctx->slots + R[q].slot0;
+        a.partials = ctx->partials + R[q].poff;
+        a.prm = ctx->table + E[q].table_off + (size_t)(i - 1) * B;
+        a.B = B;
+        a.first = (i == 1);
+        a.check_stop = (i != 1);
+        a.early = early;
+        a.tol = tol_e / (2.0 * E[q].s);
+        a.joint = 0;
+      }
+      HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_MULTI, s, [&] { return magnus::launch_csr2_ragged(r, B, s); }));
+    }
+    for (size_t q = 0; q < np; ++q)
+      if (sub < E[q].s) cur[q] = pbuf[q];
+  }
+  for (size_t q = 0; q < np; ++q)
+    if (cur[q] != E[q].dst)
+      HIP_TRY(magnus::launch_copy(cur[q], E[q].dst, (long long)R[q].P->h.H1.dim * B, s));
+  return MAGNUS_OK;
+}
+
+// Product-of-exponentials steps of the ragged batch's large problems (all of
+// batch B, B a group size), packed interleaved into their workspace slices.
+int ragged_joint_steps(magnus_ctx* ctx, std::vector<RagProblem>& R, const magnus::Scheme& S, int B, double tau,
+                       int64_t nsteps, double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  for (const RagProblem& q : R) HIP_TRY(magnus::launch_pack(q.psi(), q.v(ctx, kY), (int)q.P->h.H1.dim, B, s));
+  std::vector<double> av(B), bv(B), fv(S.q);
+  int64_t n = 0;
+  while (n < nsteps) {
+    std::vector<ColParam> table;
+    std::vector<std::vector<MultiExp>> steps;  // [step * nexp + e][problem]
+    int64_t k = n;
+    for (; k < nsteps; ++k) {
+      const size_t mark = table.size();
+      Acc trial = *acc;
+      std::vector<std::vector<MultiExp>> st(S.nexp, std::vector<MultiExp>(R.size()));
+      for (size_t q = 0; q < R.size(); ++q) {
+        const magnus_problem& P = *R[q].P;
+        const double2* src = R[q].v(ctx, kY);
+        double2* mids[2] = {R[q].v(ctx, kS2), R[q].v(ctx, kU)};
+        for (int e = 0; e < S.nexp; ++e) {
+          for (int c = 0; c < B; ++c) {
+            const double* f = P.f_nodes + ((P.batch_f == 1 ? 0 : (int64_t)(R[q].c0 + c)) * nsteps + k) * S.q;
+            for (int j = 0; j < S.q; ++j) fv[j] = f[j];
+            av[c] = S.rho[e];
+            bv[c] = scheme_b(S, e, fv.data());
+          }
+          MultiExp& E = st[e][q];
+          int rc = plan_multi(&P.h, av.data(), bv.data(), B, tau, tol_e, o, 0, &table, &E, &trial);
+          if (rc) return rc;
+          E.src = src;
+          E.dst = (e == S.nexp - 1) ? R[q].v(ctx, kY) : mids[e & 1];
+          src = E.dst;
+        }
+      }
+      if (table.size() > kTableCap) {
+        if (k == n) return fail(MAGNUS_ENOMEM, "one step needs more than the parameter table holds");
+        table.resize(mark);
+        break;
+      }
+      *acc = trial;
+      for (auto& e : st) steps.push_back(std::move(e));
+    }
+    int rc = upload_table(ctx, table, s);
+    if (rc) return rc;
+    for (const auto& E : steps)
+      if ((rc = launch_ragged_exp(ctx, R, E, B, tol_e, o->early_termination, s))) return rc;
+    n = k;
+  }
+  for (const RagProblem& q : R) HIP_TRY(magnus::launch_unpack(q.v(ctx, kY), q.psi(), (int)q.P->h.H1.dim, B, s));
+  return MAGNUS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Whole Cf4 propagations of small states, one workgroup per state.
 // ---------------------------------------------------------------------------
 struct SmallState {
@@ -961,6 +1198,7 @@ bool small_ok(magnus_ctx* ctx, const magnus_hamiltonian* h, int64_t nstates) {
 int persist_segment(magnus_ctx* ctx, const std::vector<const magnus_hamiltonian*>& hs,
                     const std::vector<SmallState>& st, const magnus::Scheme& S, double tau, int64_t n0, int64_t n1,
                     double tol_e, const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  if (int rc = flush_fused_check(ctx, s)) return rc;
   const int nst = (int)st.size();
   const int nexp = (int)(S.nexp * (n1 - n0));
   if (nst > ctx->nslots) return fail(MAGNUS_ENOMEM, "%d small states exceed %d control slots", nst, ctx->nslots);
@@ -1069,6 +1307,211 @@ int persist_steps(magnus_ctx* ctx, const std::vector<const magnus_hamiltonian*>&
   return MAGNUS_OK;
 }
 
+// Plan of one exponential of a replayed step with s substeps: the plan the
+// launch-by-launch path makes when it chooses s itself, else the smallest
+// degree for s substeps.
+bool graph_step_plan(double tau, double lo, double hi, double tol_e, int s, const magnus_leja_opts* o, ExpPlan* P) {
+  if (magnus::plan_exponential(tau, lo, hi, tol_e, o->max_degree, o->max_substeps, P) && P->lp.s == s) return true;
+  return magnus::plan_exponential_fixed_s(tau, lo, hi, tol_e, s, o->max_degree, P);
+}
+
+// ---------------------------------------------------------------------------
+// Graph replay of a single CSR state's steps.  The launches of one Magnus step
+// (every exponential's substeps and iterations, with the stop tests fused)
+// are captured once per call and replayed once per step; each launch reads
+// its Leja coefficients from a device table column indexed by a step counter
+// that the graph advances at its end.  Every step has the same launch
+// structure: per exponential k the largest substep count s_k and degree m_k
+// over the call's steps, iterations past a step's own degree inactive.
+// ---------------------------------------------------------------------------
+struct GraphPlan {
+  int nexp = 0;
+  std::vector<int> s, m;    // per exponential
+  std::vector<int> off;     // first record of exponential k in a step
+  int stride = 0;           // records per step
+  std::vector<double> lo, hi;  // enclosure of exponential k of step n at [n * nexp + k]
+  std::vector<ExpOp> ops;      // exponent of exponential k of step n
+};
+
+// Records of the graph's step table that fit the context's table memory.
+int64_t graph_table_cap(const magnus_ctx*) {
+  return (int64_t)(kTableCap * sizeof(ColParam) / sizeof(magnus::IterCoef));
+}
+
+// Whether every iteration launch of this state's exponentials makes its own
+// stop test (the condition for capturing a step: no decide kernels).
+bool graph_eligible(magnus_ctx* ctx, const magnus_hamiltonian* h, const magnus::Scheme& S) {
+  if (!ctx->graph || !ctx->fuse || ctx->timing || h->H1.format != MAGNUS_CSR || S.sixth) return false;
+  const int dim = (int)h->H1.dim;
+  const int rpb = rows_per_block(ctx, h);
+  int grid = magnus::csr2_grid(dim, rpb);
+  if (S.commutator && csr_comm_ready(ctx, h)) grid = magnus::csr3_grid(dim);
+  return grid <= magnus::kFuseMaxGrid;
+}
+
+template <class F>
+int graph_plan(magnus_ctx* ctx, const magnus_hamiltonian* h, const magnus::Scheme& S, double tau, int64_t nsteps,
+               F fval, double tol_e, const magnus_leja_opts* o, GraphPlan* G) {
+  G->nexp = S.commutator ? 1 : S.nexp;
+  const int ne = G->nexp;
+  G->s.assign(ne, 1);
+  G->m.assign(ne, 1);
+  G->lo.resize((size_t)nsteps * ne);
+  G->hi.resize((size_t)nsteps * ne);
+  G->ops.resize((size_t)nsteps * ne);
+  for (int64_t n = 0; n < nsteps; ++n) {
+    double f[3] = {0, 0, 0};
+    for (int j = 0; j < S.q; ++j) f[j] = fval(n, j);
+    for (int k = 0; k < ne; ++k) {
+      ExpOp op;
+      if (S.commutator) {
+        op = ExpOp{h, 1.0, 0.5 * (f[0] + f[1]), magnus::kSqrt3 * tau * (f[1] - f[0]) / 12.0};
+      } else {
+        op = ExpOp{h, S.rho[k], scheme_b(S, k, f), 0.0};
+      }
+      double lo, hi;
+      magnus::weyl_interval(op.a, h->H1.lam_min, h->H1.lam_max, op.b, h->H2.lam_min, h->H2.lam_max, op.kappa,
+                            h->k_min, h->k_max, &lo, &hi);
+      ExpPlan P;
+      if (!magnus::plan_exponential(tau, lo, hi, tol_e, o->max_degree, o->max_substeps, &P))
+        return fail(MAGNUS_ENOCONV, "no degree <= %d with <= %d substeps reaches tol %g", o->max_degree,
+                    o->max_substeps, tol_e);
+      G->s[k] = std::max(G->s[k], P.lp.s);
+      const size_t q = (size_t)n * ne + k;
+      G->ops[q] = op;
+      G->lo[q] = lo;
+      G->hi[q] = hi;
+    }
+  }
+  for (int64_t n = 0; n < nsteps; ++n)
+    for (int k = 0; k < ne; ++k) {
+      ExpPlan P;
+      const size_t q = (size_t)n * ne + k;
+      if (!graph_step_plan(tau, G->lo[q], G->hi[q], tol_e, G->s[k], o, &P))
+        return fail(MAGNUS_ENOCONV, "no degree <= %d reaches tol %g with %d substeps", o->max_degree, tol_e, G->s[k]);
+      G->m[k] = std::max(G->m[k], P.lp.m);
+    }
+  G->off.assign(ne, 0);
+  G->stride = 0;
+  for (int k = 0; k < ne; ++k) {
+    G->off[k] = G->stride;
+    G->stride += G->s[k] * G->m[k];
+  }
+  if (G->stride > graph_table_cap(ctx)) return fail(MAGNUS_ENOMEM, "step table too large for graph replay");
+  return MAGNUS_OK;
+}
+
+// Coefficient records of steps [n0, n1) in the layout a captured step reads
+// (record off[k] + sub * m[k] + i - 1 of each step).
+int graph_fill(const GraphPlan& G, double tau, int64_t n0, int64_t n1, double tol_e, const magnus_leja_opts* o,
+               Acc* acc, std::vector<magnus::IterCoef>* out) {
+  const auto& xi = magnus::leja_points();
+  const int ne = G.nexp;
+  out->assign((size_t)(n1 - n0) * G.stride, magnus::IterCoef{});
+  for (int64_t n = n0; n < n1; ++n)
+    for (int k = 0; k < ne; ++k) {
+      const size_t q = (size_t)n * ne + k;
+      ExpPlan P;
+      if (!graph_step_plan(tau, G.lo[q], G.hi[q], tol_e, G.s[k], o, &P))
+        return fail(MAGNUS_ENOCONV, "no degree <= %d reaches tol %g", o->max_degree, tol_e);
+      const ExpOp& op = G.ops[q];
+      const int m = P.lp.m, ns = G.s[k];
+      for (int sub = 0; sub < ns; ++sub)
+        for (int i = 1; i <= m; ++i) {
+          magnus::IterCoef& c = (*out)[(size_t)(n - n0) * G.stride + G.off[k] + (size_t)sub * G.m[k] + (i - 1)];
+          c.a1 = P.scale * op.a;
+          c.a2 = P.scale * op.b;
+          c.kap = P.scale * op.kappa;
+          c.sigma = P.scale * P.c + xi[i - 1];
+          c.dre = P.d[i].real();
+          c.dim = P.d[i].imag();
+          c.d0re = P.d[0].real();
+          c.d0im = P.d[0].imag();
+          c.dabs = std::abs(P.d[i]);
+          c.d0abs = std::abs(P.d[0]);
+          c.prev_dabs = i >= 2 ? std::abs(P.d[i - 1]) : 0.0;
+          c.tol = tol_e / (2.0 * ns);
+          c.active = 1;
+        }
+      acc->exponentials += 1;
+      acc->substeps += ns;
+      acc->planned += (int64_t)m * ns;
+      acc->max_m = std::max(acc->max_m, m);
+      acc->max_s = std::max(acc->max_s, ns);
+      acc->max_bound = std::max(acc->max_bound, P.lp.bound);
+    }
+  return MAGNUS_OK;
+}
+
+void graph_release(magnus_ctx* ctx) {
+  if (ctx->graph_x) (void)hipGraphExecDestroy(ctx->graph_x);
+  if (ctx->graph_g) (void)hipGraphDestroy(ctx->graph_g);
+  ctx->graph_x = nullptr;
+  ctx->graph_g = nullptr;
+}
+
+// Capture the launches of one step of state y (in place) on the context's
+// capture stream: the exponentials in the scheme's order, each launch bound
+// to its table column, then the step counter's advance.
+int graph_capture(magnus_ctx* ctx, const magnus_hamiltonian* h, const magnus::Scheme& S, const GraphPlan& G,
+                  double2* y, double tol_e, int early) {
+  if (ctx->graph_x) {
+    // the previous call's replays must have finished before its graph goes
+    HIP_TRY(hipEventSynchronize(ctx->graph_done));
+    graph_release(ctx);
+  }
+  if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = ctx->cap_stream;
+  const magnus::IterCoef* base = reinterpret_cast<const magnus::IterCoef*>(ctx->table);
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  int rc = MAGNUS_OK;
+  double2* mids[2] = {ctx->vec(kS2), ctx->vec(kU)};
+  const double2* src = y;
+  for (int k = 0; k < G.nexp && rc == MAGNUS_OK; ++k) {
+    // structure only: the coefficients come from the table
+    ExpPlan T;
+    T.scale = 1.0;
+    T.lp = magnus::LejaPlan{G.m[k], G.s[k], 0.0};
+    T.d.assign((size_t)G.m[k] + 1, std::complex<double>(1.0, 0.0));
+    const TableRef tab{base + G.off[k], G.stride, ctx->gctr};
+    double2* dst = (k == G.nexp - 1) ? y : mids[k & 1];
+    const ExpOp op{h, 1.0, 1.0, S.commutator ? 1.0 : 0.0};
+    rc = enqueue_exponential(ctx, op, T, src, dst, tol_e / (2.0 * G.s[k]), early, &tab, cs);
+    src = dst;
+  }
+  if (rc == MAGNUS_OK && magnus::launch_step_advance(ctx->gctr, cs) != hipSuccess)
+    rc = fail(MAGNUS_EHIP, "step counter launch during capture");
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc != MAGNUS_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != MAGNUS_OK ? rc : fail(MAGNUS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  ctx->graph_g = g;
+  HIP_TRY(hipGraphInstantiate(&ctx->graph_x, g, nullptr, nullptr, 0));
+  if (!ctx->graph_done) HIP_TRY(hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming));
+  return MAGNUS_OK;
+}
+
+// Replay steps [n0, n1): table chunks uploaded behind the previous replays,
+// the counter set to the chunk's first step, one graph launch per step.
+int graph_replay(magnus_ctx* ctx, const GraphPlan& G, double tau, int64_t n0, int64_t n1, double tol_e,
+                 const magnus_leja_opts* o, Acc* acc, hipStream_t s) {
+  int64_t per = std::max<int64_t>(1, graph_table_cap(ctx) / G.stride);
+  if (ctx->graph_chunk > 0) per = std::min<int64_t>(per, ctx->graph_chunk);
+  for (int64_t c0 = n0; c0 < n1; c0 += per) {
+    const int64_t c1 = std::min(n1, c0 + per);
+    int rc = graph_fill(G, tau, c0, c1, tol_e, o, acc, &ctx->graph_table);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->table, ctx->graph_table.data(), sizeof(magnus::IterCoef) * ctx->graph_table.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(magnus::launch_step_set(ctx->gctr, 0, s));
+    for (int64_t n = c0; n < c1; ++n) HIP_TRY(hipGraphLaunch(ctx->graph_x, s));
+  }
+  HIP_TRY(hipEventRecord(ctx->graph_done, s));
+  return MAGNUS_OK;
+}
+
 int check_batch(magnus_ctx* ctx, int32_t batch) {
   if (batch < 1) return fail(MAGNUS_EINVAL, "batch %d < 1", batch);
   if (batch > ctx->max_batch) return fail(MAGNUS_ENOMEM, "batch %d exceeds workspace max_batch %d", batch, ctx->max_batch);
@@ -1093,12 +1536,12 @@ constexpr size_t kNaAlign = 256;
 constexpr size_t na_round(size_t b) { return (b + kNaAlign - 1) / kNaAlign * kNaAlign; }
 constexpr size_t kNaVecBytes = (size_t)kNumVec * (size_t)kNoAllocMaxDim * sizeof(double2);
 constexpr int64_t kNaGrid = kNoAllocMaxDim / 8 + 2;  // as magnus_create: 8 rows per smallest row block
-constexpr size_t kNaPartials = 2 * (size_t)kNaGrid + 64;
+constexpr size_t kNaPartials = 4 * (size_t)kNaGrid + 64;  // two halves for the fused stop tests
 constexpr int64_t kNaScanLen = 2 * (kNoAllocMaxDim / 4 + 2) + 3 * (kNoAllocMaxDim / 256 + 2);
 constexpr size_t kNaPartialOff = kNaVecBytes;
 constexpr size_t kNaScanOff = kNaPartialOff + na_round(kNaPartials * sizeof(double));
 constexpr size_t kNaSlotOff = kNaScanOff + na_round((size_t)kNaScanLen * sizeof(double));
-constexpr size_t kNoAllocBytes = kNaSlotOff + na_round(sizeof(Slot));  // 16.8 MiB
+constexpr size_t kNoAllocBytes = kNaSlotOff + na_round(sizeof(Slot));  // 17.0 MiB
 constexpr int kNaMaxDevices = 64;
 }  // namespace
 
@@ -1134,6 +1577,7 @@ int noalloc_context(magnus_ctx** out) {
     c.nslots = 1;
     c.persist = 0;
     if (const char* v = getenv("MAGNUS_CSR_VARIANT")) c.csr_variant = atoi(v);
+    if (const char* v = getenv("MAGNUS_FUSE")) c.fuse = atoi(v);
     c.vecs = reinterpret_cast<double2*>(base);  // last: marks the device's context ready
   }
   *out = &c;
@@ -1163,6 +1607,18 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   c->scan_len = 2 * (max_dim / 4 + 2) + 3 * (max_dim / 256 + 2);
   c->nslots = std::max<int>(256, max_batch);
   if (const char* v = getenv("MAGNUS_PERSIST")) c->persist = atoi(v);
+  if (const char* v = getenv("MAGNUS_FUSE")) c->fuse = atoi(v);
+  if (const char* v = getenv("MAGNUS_GRAPH")) c->graph = atoi(v);
+  if (const char* v = getenv("MAGNUS_GRAPH_STEPS")) c->graph_chunk = atoi(v);
+  if (const char* v = getenv("MAGNUS_RAGGED_JOINT")) c->ragged_joint = atoi(v);
+  if (const char* v = getenv("MAGNUS_DENSE_RPW")) {
+    const int r = atoi(v);
+    c->dense_rpw_env = (r == 1 || r == 2 || r == 4) ? r : 0;
+  }
+  if (const char* v = getenv("MAGNUS_MFMA_TILE")) {
+    const int t = atoi(v);
+    c->mfma_tile_env = (t >= 0 && t < magnus::kMfmaTiles) ? t : -1;
+  }
   const size_t nvec = (size_t)kNumVec * (size_t)max_dim * (size_t)max_batch;
   hipError_t e = hipMalloc(&c->vecs, sizeof(double2) * nvec);
   if (e == hipSuccess) e = hipMalloc(&c->slots, sizeof(Slot) * c->nslots);
@@ -1175,6 +1631,7 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
   c->npartials = std::max(c->npartials, (size_t)magnus::kDotPartials + 64);
   if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->npartials);
   if (e == hipSuccess) e = hipMalloc(&c->scan, sizeof(double) * (size_t)c->scan_len);
+  if (e == hipSuccess) e = hipMalloc(&c->gctr, 256);
   if (e == hipSuccess) e = hipMemset(c->slots, 0, sizeof(Slot) * c->nslots);
   if (e == hipSuccess) e = hipMemset(c->vecs, 0, sizeof(double2) * nvec);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -1396,13 +1853,113 @@ int magnus_dense_m6_prepare(magnus_ctx* ctx, magnus_hamiltonian* h, magnus_strea
   return MAGNUS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Dense terms: the GEMV iteration with 1, 2 and 4 rows per wave (two terms),
+// and for batches the FP64-MFMA group iteration with each tile shape on the
+// batch's states (one term, as a shared field assembles the exponent, when
+// the context holds an assembly buffer; else two), 5 timed launches each.
+int autotune_dense(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch, int32_t* variant, int32_t* group,
+                   double* variant_us, double* group_us, hipStream_t s) {
+  int rc = begin_call(ctx, s);
+  if (rc) return rc;
+  const int dim = (int)h->H1.dim;
+  const size_t nvec = (size_t)ctx->max_dim * (size_t)ctx->max_batch;
+  for (int k : {kA, kB, kS0, kY}) HIP_TRY(hipMemsetAsync(ctx->vec(k), 0, sizeof(double2) * nvec, s));
+  const double2* D1 = reinterpret_cast<const double2*>(h->H1.val);
+  const double2* D2 = reinterpret_cast<const double2*>(h->H2.val);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  constexpr int kReps = 5;
+  auto time_us = [&](auto f, double* us) -> hipError_t {
+    hipError_t e = f();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < kReps && e == hipSuccess; ++r) e = f();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    *us = 1e3 * (double)ms / kReps;
+    return e;
+  };
+  hipError_t err = hipSuccess;
+  IterArgs a{};
+  a.x1 = a.x2 = a.wcur = ctx->vec(kA);
+  a.wout = ctx->vec(kB);
+  a.pacc = ctx->vec(kS0);
+  a.slot = ctx->slots;
+  a.partials = ctx->partials;
+  a.a1 = a.a2 = 1.0;
+  a.first = 1;
+  int best_rpw = 2;
+  double best = INFINITY;
+  const int rpws[3] = {1, 2, 4};
+  for (int q = 0; q < 3 && err == hipSuccess; ++q) {
+    double us = 0.0;
+    err = time_us([&] { return magnus::launch_dense2_iter(D1, D2, dim, h->H1.ld, a, s, rpws[q]); }, &us);
+    if (variant_us) variant_us[q] = us;
+    if (us < best) {
+      best = us;
+      best_rpw = rpws[q];
+    }
+  }
+  if (variant_us)
+    for (int q = 3; q < kTuneVariants; ++q) variant_us[q] = NAN;
+  int best_tile = 0;
+  double best_t = INFINITY;
+  if (err == hipSuccess && batch > 1) {
+    std::vector<ColParam> table(batch);
+    for (ColParam& c : table) c.a1 = c.a2 = 1.0;
+    if ((rc = upload_table(ctx, table, s))) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+    const bool one = ctx->assembled && ctx->assembled_dim >= dim;
+    for (int t = 0; t < magnus::kMfmaTiles && err == hipSuccess; ++t) {
+      MultiArgs m{};
+      m.x = ctx->vec(kY);
+      m.wout = ctx->vec(kA);
+      m.pacc = ctx->vec(kB);
+      m.slots = ctx->slots;
+      m.partials = ctx->partials;
+      m.prm = ctx->table;
+      m.B = batch;
+      m.first = 1;
+      double us = 0.0;
+      err = time_us([&] { return magnus::launch_dense_mfma(one ? 1 : 2, D1, D2, h->H1.ld, dim, m, s, t); }, &us);
+      if (group_us) group_us[t] = us;
+      if (us < best_t) {
+        best_t = us;
+        best_tile = t;
+      }
+    }
+  } else if (group_us) {
+    for (int t = 0; t < magnus::kMfmaTiles; ++t) group_us[t] = NAN;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(MAGNUS_EHIP, "autotune: %s", hipGetErrorString(err));
+  const auto key = std::make_pair(h->H1.val, h->H1.dim);
+  ctx->tuned_dense_rpw[key] = best_rpw;
+  if (batch > 1) ctx->tuned_mfma[key] = best_tile;
+  if (variant) *variant = best_rpw;
+  if (group) *group = batch > 1 ? best_tile : 0;
+  return MAGNUS_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch, int32_t* variant,
                     int32_t* group, double* variant_us, double* group_us, magnus_stream stream) {
   int rc = check_ham(ctx, h, 0);
   if (rc) return rc;
   if ((rc = check_batch(ctx, batch))) return rc;
-  if (h->H1.format != MAGNUS_CSR) return fail(MAGNUS_EINVAL, "magnus_autotune tunes CSR kernels");
   hipStream_t s = (hipStream_t)stream;
+  if (h->H1.format == MAGNUS_DENSE) return autotune_dense(ctx, h, batch, variant, group, variant_us, group_us, s);
   if ((rc = begin_call(ctx, s))) return rc;
   if ((rc = ensure_valid(ctx, h, s))) return rc;
   const int dim = (int)h->H1.dim;
@@ -1515,6 +2072,13 @@ int magnus_destroy(magnus_ctx* ctx) {
   if (ctx->pm_ws) (void)hipFree(ctx->pm_ws);
   if (ctx->partials) (void)hipFree(ctx->partials);
   if (ctx->scan) (void)hipFree(ctx->scan);
+  if (ctx->graph_x || ctx->graph_g) {
+    if (ctx->graph_done) (void)hipEventSynchronize(ctx->graph_done);
+    graph_release(ctx);
+  }
+  if (ctx->graph_done) (void)hipEventDestroy(ctx->graph_done);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->gctr) (void)hipFree(ctx->gctr);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   delete ctx;
   return MAGNUS_OK;
@@ -1588,6 +2152,7 @@ int apply_term(magnus_ctx* ctx, const magnus_term& t, const double2* x, double2*
 // Re(x^H y) on the host (one device dot product and a wait).
 int dot_re(magnus_ctx* ctx, const double2* x, const double2* y, int64_t n, double* out, hipStream_t s) {
   double2* dev_out = reinterpret_cast<double2*>(ctx->partials + magnus::kDotPartials);
+  if (int rc = flush_fused_check(ctx, s)) return rc;
   HIP_TRY(magnus::launch_cdot(x, 1, y, 1, n, ctx->partials, dev_out, s));
   double2 h;
   HIP_TRY(hipMemcpyAsync(&h, dev_out, sizeof(double2), hipMemcpyDeviceToHost, s));
@@ -1827,6 +2392,16 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
     const int64_t k = ((n / every_k) + 1) * every_k;
     return std::min(k, nsteps);
   };
+  // one state on the grid path with every stop test fused: one step captured,
+  // replayed once per step
+  GraphPlan G;
+  const bool use_graph = batch == 1 && !small && tau != 0.0 && nsteps >= 2 && graph_eligible(ctx, h, S);
+  if (use_graph) {
+    if ((rc = graph_plan(ctx, h, S, tau, nsteps, [&](int64_t k, int j) { return fval(0, k, j); }, tol_e, opts, &G)))
+      return rc;
+    if ((rc = flush_fused_check(ctx, s))) return rc;
+    if ((rc = graph_capture(ctx, h, S, G, st, tol_e, opts->early_termination))) return rc;
+  }
   int64_t n = 0;
   while (n < nsteps) {
     const int64_t stop = next_stop(n);
@@ -1842,6 +2417,8 @@ int propagate(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t method, doub
                             [&](int cc, int64_t k, int j) { return fval(c + cc, k, j); }, tol_e, opts, &acc, s);
         if (rc) return rc;
         HIP_TRY(magnus::launch_unpack(ctx->vec(kY), st + c * dim, (int)dim, g, s));
+      } else if (use_graph) {
+        if ((rc = graph_replay(ctx, G, tau, n, stop, tol_e, opts, &acc, s))) return rc;
       } else {
         for (int64_t k = n; k < stop; ++k) {
           double2* y = st + c * dim;
@@ -1939,6 +2516,48 @@ int magnus_propagate_ragged(magnus_ctx* ctx, const magnus_problem* probs, int32_
     } else {
       big.push_back(i);
     }
+  }
+  // the large problems together when they have the same batch and fit the
+  // workspace at once: each split into groups of JB states (the group size
+  // tuned for the largest of them, else the largest that divides the batch),
+  // one launch per Leja iteration for all groups, their control slots after
+  // the small states' (no reset, no host wait between problems)
+  bool joint = ctx->ragged_joint && !S.commutator && big.size() >= 2;
+  int JB = 0;
+  if (joint) {
+    const int batch = probs[big[0]].batch;
+    int largest = big[0];
+    for (int i : big)
+      if (probs[i].h.H1.dim > probs[largest].h.H1.dim) largest = i;
+    JB = group_for(ctx, &probs[largest].h, batch);
+    while (JB > 1 && batch % JB != 0) JB /= 2;
+    size_t vtot = 0, ptot = 0, groups = 0;
+    for (int i : big) {
+      const magnus_problem& P = probs[i];
+      joint = joint && P.h.H1.format == MAGNUS_CSR && P.batch == batch;
+      vtot += (size_t)P.h.H1.dim * batch;
+      if (JB >= 2) ptot += (size_t)magnus::ragged_grid((int)P.h.H1.dim, JB) * JB * 2 * (batch / JB);
+      groups += JB >= 2 ? (size_t)(batch / JB) : 0;
+    }
+    joint = joint && JB >= 2 && JB <= ctx->max_batch && groups <= (size_t)magnus::kMaxRagged &&
+            vtot <= (size_t)ctx->max_dim * (size_t)ctx->max_batch && ptot <= ctx->npartials &&
+            sst.size() + groups * (size_t)JB <= (size_t)ctx->nslots;
+  }
+  if (joint && nsteps > 0) {
+    std::vector<RagProblem> R;
+    size_t voff = 0, poff = 0;
+    int slot0 = (int)sst.size();
+    for (int i : big) {
+      const magnus_problem& P = probs[i];
+      for (int c0 = 0; c0 < P.batch; c0 += JB) {
+        R.push_back(RagProblem{&P, c0, voff, slot0, poff});
+        voff += (size_t)P.h.H1.dim * JB;
+        poff += (size_t)magnus::ragged_grid((int)P.h.H1.dim, JB) * JB * 2;
+        slot0 += JB;
+      }
+    }
+    if ((rc = ragged_joint_steps(ctx, R, S, JB, tau, nsteps, tol_e, opts, &acc, s))) return rc;
+    big.clear();
   }
   // the large problems first: each is one batched propagation (which resets the control slots)
   for (int i : big) {
@@ -2045,6 +2664,7 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
       HIP_TRY(hipMemcpyAsync(ck + slot * dim, mu, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
     }
   }
+  if ((rc = flush_fused_check(ctx, s))) return rc;
   HIP_TRY(magnus::launch_cdot(tgt, 1, mu, 1, dim, ctx->partials, g + 2 * nsteps, s));
   HIP_TRY(hipMemcpyAsync(lam, tgt, sizeof(double2) * dim, hipMemcpyDeviceToDevice, s));
 
@@ -2081,6 +2701,7 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
       // g_a(n) = lambda_{n+1}^H L_a phi_n
       HIP_TRY(magnus::launch_frechet_init(seg_phi + (n - n0) * dim, X2, (int)dim, s));
       if ((rc = launch_multi(ctx, h, A, tol_e, opts->early_termination, s))) return rc;
+      if ((rc = flush_fused_check(ctx, s))) return rc;
       HIP_TRY(magnus::launch_cdot(lam, 1, Y2, 2, dim, ctx->partials, g + 2 * n, s));
       // mu_n = E_a^H lambda_{n+1}
       rc = run_exponential(ctx, ExpOp{h, 0.5, gamma_of(n), 0.0}, -tau, lam, mu, tol_e, opts, &acc, s);
@@ -2088,6 +2709,7 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
       // g_b(n) = mu_n^H L_b psi_n
       HIP_TRY(magnus::launch_frechet_init(seg_psi + (n - n0) * dim, X2, (int)dim, s));
       if ((rc = launch_multi(ctx, h, Bx, tol_e, opts->early_termination, s))) return rc;
+      if ((rc = flush_fused_check(ctx, s))) return rc;
       HIP_TRY(magnus::launch_cdot(mu, 1, Y2, 2, dim, ctx->partials, g + 2 * n + 1, s));
       // lambda_n = E_b^H mu_n
       rc = run_exponential(ctx, ExpOp{h, 0.5, beta_of(n), 0.0}, -tau, mu, lam, tol_e, opts, &acc, s);

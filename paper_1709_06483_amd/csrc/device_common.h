@@ -63,5 +63,113 @@ __device__ __forceinline__ void leja_verdict(Slot* S, bool first, bool early, do
   S->iters_total += 1;
 }
 
+// The launch's arguments with the coefficients of the current step read from
+// its table column when it runs from a replayed graph (uniform scalar loads).
+__device__ __forceinline__ IterArgs resolve_args(const IterArgs& in) {
+  IterArgs a = in;
+  if (!in.coef) return a;
+  const IterCoef* c = in.coef + (long long)(*in.step) * in.coef_stride;
+  if (!in.unit_a) {
+    a.a1 = c->a1;
+    a.a2 = c->a2;
+  }
+  a.kap = c->kap;
+  a.sigma = c->sigma;
+  a.d = make_double2(c->dre, c->dim);
+  a.d0 = make_double2(c->d0re, c->d0im);
+  a.dabs = c->dabs;
+  a.d0abs = c->d0abs;
+  a.prev_dabs = c->prev_dabs;
+  a.tol = c->tol;
+  a.skip = !c->active;
+  return a;
+}
+
+// Whether an iteration launch must return at once because its substep has
+// stopped.  Without a.fused the verdict of the previous iteration is in the
+// slot (written by the decide kernel launched after it).  With a.fused, every
+// workgroup reduces the previous iteration's partials itself in one fixed
+// order (each thread a fixed subset in order, then the waves in order), so
+// every workgroup reaches the same verdict; workgroup 0 records it in the
+// slot and counts the iteration.  Called by every thread of the workgroup;
+// the result is uniform over it.  Slot fields written here are never read by
+// the same launch: term[] is double-buffered by iteration parity, vnorm is
+// written on the second iteration only, when every workgroup computes it.
+// lds: kFuseLds doubles of the caller's LDS, free to reuse once this returns.
+constexpr int kFuseLds = 40;
+__device__ __forceinline__ bool iteration_stopped(const IterArgs& a, double* lds) {
+  if (!a.fused) return a.skip || (a.check_stop && load_stopped(a.slot));
+  Slot* S = a.slot;
+  const int tid = threadIdx.x;
+  if (!a.check_stop) {  // a substep's first iteration: it always runs
+    if (blockIdx.x == 0 && tid == 0) {
+      S->stopped = 0;
+      S->iters_sub = 1;
+      S->iters_total += 1;
+    }
+    return false;
+  }
+  // The partial sums are loaded before a replayed launch's record (which
+  // says whether the iteration is past its step's degree) is looked at, so
+  // the two latencies overlap; a skipped iteration discards the sums.
+  double* fz_w = lds;       // per-wave sums (at most 16 waves)
+  double* fz_v = lds + 16;
+  if (tid == 0) lds[32] = load_stopped(S) ? 1.0 : 0.0;
+  const int n = a.prev_grid, nt = blockDim.x;
+  const bool vfirst = a.iter == 2;  // the previous iteration was the substep's first
+  const double* P = a.prev_partials;
+  constexpr int kU = 8;
+  double sw = 0.0, sv = 0.0;
+  for (int k0 = 0; k0 < n; k0 += kU * nt) {
+    double w[kU], v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * nt + tid;
+      w[u] = k < n ? P[k] : 0.0;
+      v[u] = (vfirst && k < n) ? P[n + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      sw += w[u];
+      sv += v[u];
+    }
+  }
+  sw = wave_sum(sw);
+  sv = wave_sum(sv);
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  if (lane == 0) {
+    fz_w[wv] = sw;
+    fz_v[wv] = sv;
+  }
+  __syncthreads();
+  // past this step's degree (uniform: scalar loads), or stopped by an earlier verdict of this substep
+  if (a.skip || lds[32] != 0.0) return true;
+  double tw = 0.0, tv = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    tw += fz_w[w];
+    tv += fz_v[w];
+  }
+  __syncthreads();  // every wave has read the sums: the caller may reuse lds
+  const double vn = vfirst ? sqrt(tv) : S->vnorm;
+  const double prev = vfirst ? a.d0abs * vn : S->term[a.iter & 1];  // iteration iter-2's term
+  const double term = a.prev_dabs * sqrt(tw);
+  const double est = term + prev;
+  const bool bad = !isfinite(tw) || !isfinite(vn);
+  const bool stop = bad || (a.early && est <= a.tol * vn);
+  if (blockIdx.x == 0 && tid == 0) {
+    if (bad) S->status |= 1;
+    if (vfirst) S->vnorm = vn;
+    S->term[(a.iter - 1) & 1] = term;
+    S->last_est = est;
+    if (stop) {
+      S->stopped = 1;
+    } else {
+      S->iters_sub = a.iter;
+      S->iters_total += 1;
+    }
+  }
+  return stop;
+}
+
 }  // namespace dev
 }  // namespace magnus

@@ -9,7 +9,9 @@ namespace magnus {
 // Per-state control block in device memory.  One Leja substep runs as a
 // sequence of iteration kernels, each followed by a one-workgroup kernel that
 // reduces the norm partials in a fixed order, evaluates the early-termination
-// test and writes the verdict here for the next iteration to read.
+// test and writes the verdict here for the next iteration to read; or, on
+// small grids, with that reduction and test made at the start of the next
+// iteration kernel by each of its workgroups (IterArgs::fused).
 struct Slot {
   unsigned int counter;   // unused (kept zero)
   int stopped;            // 1: the current substep has terminated early
@@ -19,6 +21,7 @@ struct Slot {
   double vnorm;           // |v| of the current substep
   double prev_term;       // |d_{i-1}| |w_{i-1}|
   double last_est;        // last early-termination estimate
+  double term[2];         // fused stop test: |d_i| |w_i| of iteration i at term[i & 1]
 };
 
 struct CsrDev {
@@ -33,6 +36,19 @@ enum IterMode : int {
   kLejaComm = 2,   // y = a1 x2 + a2 x1 + i k (H1 x1 - H2 x2), then the Leja update
   kSplitComm = 3,  // out1 = a1 x + i k H2 x, out2 = a2 x - i k H1 x with x = x1 = x2 = wcur
                    // (streamed kernel only; kLeja over out1, out2 with a1 = a2 = 1 completes it)
+};
+
+// The coefficients of one Leja iteration of one Magnus step, read from device
+// memory by launches that a captured graph replays once per step: record
+// coef[step * stride] of the launch's table column, with `step` a device
+// counter the graph advances at its end.  Iterations past the step's own
+// degree (the graph holds the largest degree of the call) are inactive.
+struct IterCoef {
+  double a1, a2, kap, sigma;
+  double dre, dim, d0re, d0im;
+  double dabs, d0abs, prev_dabs, tol;
+  int active;
+  int pad;
 };
 
 // One Leja iteration: w_i = X w_{i-1} - xi_{i-1} w_{i-1}, p += d_i w_i, where
@@ -56,6 +72,23 @@ struct IterArgs {
   int early;            // early termination enabled
   int first;            // first iteration of a substep
   int check_stop;       // return at once if the substep has stopped
+  // Fused stop test (no decide kernel between iterations): every workgroup of
+  // iteration `iter` reduces iteration iter-1's partials itself, in one fixed
+  // order, and applies the early-termination test; workgroup 0 records the
+  // verdict and counts the iteration in the slot.
+  int fused;
+  int iter;                    // iteration index within the substep (1-based)
+  const double* prev_partials; // iteration iter-1's partials (its |v|^2 partials follow when iter == 2)
+  int prev_grid;               // workgroups of iteration iter-1
+  double prev_dabs;            // |d_{iter-1}|
+  // Table mode (graph replay): the coefficients above come from
+  // coef[*step * coef_stride]; unit_a keeps a1 = a2 = 1 (the second pass of a
+  // streamed commutator iteration); skip is set for an inactive record.
+  const IterCoef* coef;
+  const int* step;
+  int coef_stride;
+  int unit_a;
+  int skip;
 };
 
 // Row-block selector of launch_csr2_iter: 16 or 64 rows per workgroup with
@@ -125,13 +158,27 @@ int dense_gershgorin_grid(int dim);
 
 // Dense Leja iteration (mode kLeja only): two terms, or one (an assembled
 // exponent) when H2 is null.
+// rpw: rows per wave (1, 2 or 4).
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
-                              const IterArgs& a, hipStream_t s);
-int dense2_grid(int dim, int nterms);
+                              const IterArgs& a, hipStream_t s, int rpw = 2);
+int dense2_grid(int dim, int nterms, int rpw = 2);
 
 // Reduce the norm partials of the iteration launched just before (grid
 // workgroups) and write the early-termination verdict into the slot.
 hipError_t launch_leja_decide(const IterArgs& a, int grid, hipStream_t s);
+// After the last fused iteration of a call: flag a non-finite norm of that
+// iteration (a.prev_partials, a.prev_grid, a.iter = the iteration after it)
+// unless its substep had stopped.
+hipError_t launch_leja_final_check(const IterArgs& a, hipStream_t s);
+// Largest grid of an iteration launch that makes its own stop decision
+// (each workgroup reads every partial sum of the previous iteration; measured
+// on chains, Cf4 steps/s with the decide kernel / fused: n = 13 (512
+// workgroups) 7,786 / 9,448, n = 14 (1,024) 6,664 / 7,525, n = 15 (2,048)
+// 4,987 / 5,095, n = 16 (2,048 wave tiles) 3,796 / 3,640).
+constexpr int kFuseMaxGrid = 1024;
+// Step counter of graph replays: set to zero, advanced by one.
+hipError_t launch_step_set(int* ctr, int value, hipStream_t s);
+hipError_t launch_step_advance(int* ctr, hipStream_t s);
 
 // ---- several states at once (states interleaved: element (row, b) at row*B + b) ----
 
@@ -172,6 +219,28 @@ hipError_t launch_csr2_multi(int mode, const CsrDev& t1, const CsrDev& t2, int d
                              hipStream_t s);
 // Per-column (or joint) reduction of the partials and stop verdicts.
 hipError_t launch_multi_decide(const MultiArgs& a, int grid, hipStream_t s);
+
+// Several problems of B interleaved states each (own CSR terms, states,
+// coefficients, slots and partials) in one launch per Leja iteration, then
+// one decision launch for all their columns.  block0, col0, keep_entries and
+// nblocks are filled by launch_csr2_ragged; problem q's partials take
+// ragged_grid(dim, B) * B * 2 doubles.
+constexpr int kMaxRagged = 8;
+struct RaggedProblem {
+  CsrDev t1, t2;
+  int dim;
+  int block0;        // first workgroup of the problem
+  int col0;          // first decision workgroup of the problem
+  int keep_entries;  // matrix entries read with normal loads (MALL-resident)
+  MultiArgs a;
+};
+struct RaggedArgs {
+  RaggedProblem p[kMaxRagged];
+  int np;
+  int nblocks;
+};
+int ragged_grid(int dim, int B);
+hipError_t launch_csr2_ragged(RaggedArgs r, int B, hipStream_t s);
 // Interleave / de-interleave B states of dim entries (optionally scaling by a
 // per-state phase is not needed: plain copies).
 hipError_t launch_pack(const double2* src, double2* dst, int dim, int B, hipStream_t s);
@@ -180,8 +249,11 @@ hipError_t launch_unpack(const double2* src, double2* dst, int dim, int B, hipSt
 // Dense group iteration as an FP64 MFMA GEMM fused with the Leja update
 // (nterms = 1: H1 only, y_b = a1_b H1 w_b; nterms = 2: y_b = H1 (a1_b w_b) + H2 (a2_b w_b)).
 // Partials are written per 32-row block: decide with dense_mfma_row_blocks(dim).
+// tile: 0 32 x 64 with K split in two (default), 1 32 x 64, 2 64 x 64,
+// 3 64 x 64 with K split in two, 4 32 x 128 with K split in two (rows x states).
+constexpr int kMfmaTiles = 5;
 hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
-                             const MultiArgs& a, hipStream_t s);
+                             const MultiArgs& a, hipStream_t s, int tile = 0);
 int dense_mfma_row_blocks(int dim);
 // out = ca H1 + cb H2 (dim x dim, row stride ld in, dim out).
 // out = ca H1 + cb H2 + ck K (H1, H2 with row stride ld; K, if not null, and

@@ -103,6 +103,27 @@ __global__ __launch_bounds__(kDecideThreads) void leja_decide_kernel(IterArgs a,
   }
 }
 
+// After the last iteration of a call whose stop tests were fused into the
+// iteration kernels: no later launch reduces that iteration's partials, so
+// this one checks them for non-finite norms (unless the substep had stopped
+// before it, leaving stale partials).
+__global__ __launch_bounds__(kDecideThreads) void leja_final_check_kernel(IterArgs a) {
+  __shared__ double red[2][kDecideThreads / 64];
+  if (load_stopped(a.slot)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double sw = decide_sum(a.prev_partials, a.prev_grid, tid);
+  double sv = a.iter == 2 ? decide_sum(a.prev_partials + a.prev_grid, a.prev_grid, tid) : 0.0;
+  sw = wave_sum(sw);
+  sv = wave_sum(sv);
+  if (lane == 0) { red[0][wv] = sw; red[1][wv] = sv; }
+  __syncthreads();
+  if (tid == 0) {
+    double tw = 0.0, tv = 0.0;
+    for (int w = 0; w < kDecideThreads / 64; ++w) { tw += red[0][w]; tv += red[1][w]; }
+    if (!isfinite(tw) || !isfinite(tv)) a.slot->status |= 1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Two-term CSR iteration.  A workgroup owns ROWS consecutive rows; all of its
 // threads stream the rows' nonzeros of both terms (coalesced, non-temporal,
@@ -112,13 +133,15 @@ __global__ __launch_bounds__(kDecideThreads) void leja_decide_kernel(IterArgs a,
 // processing the workgroup's nonzeros in chunks of CAP.
 // ---------------------------------------------------------------------------
 template <int ROWS, int MODE>
-__global__ __launch_bounds__(kThreads) void csr2_iter_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+__global__ __launch_bounds__(kThreads) void csr2_iter_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a_in) {
+  const IterArgs a = resolve_args(a_in);
   constexpr int LPR = kThreads / ROWS;
   constexpr int CAP = ROWS * 32;
   constexpr int U = 4;
   __shared__ d2 prod[CAP];
   __shared__ int rps[2][ROWS + 1];
-  if (a.check_stop && load_stopped(a.slot)) return;
+  static_assert(2 * CAP >= kFuseLds, "stop-test scratch");
+  if (iteration_stopped(a, reinterpret_cast<double*>(prod))) return;
 
   const int tid = threadIdx.x;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -230,7 +253,8 @@ __global__ __launch_bounds__(kThreads) void csr2_iter_kernel(CsrDev t1, CsrDev t
 // consecutive rows with coalesced stores.
 // ---------------------------------------------------------------------------
 template <int ROWS, int MODE>
-__global__ __launch_bounds__(kThreads) void csr2_rowlane_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a) {
+__global__ __launch_bounds__(kThreads) void csr2_rowlane_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a_in) {
+  const IterArgs a = resolve_args(a_in);
   constexpr int NW = kThreads / ROWS;  // entry groups per row
   constexpr int CAP = ROWS * 32;
   constexpr int U = CAP / kThreads;
@@ -239,7 +263,8 @@ __global__ __launch_bounds__(kThreads) void csr2_rowlane_kernel(CsrDev t1, CsrDe
   __shared__ int rps[2][ROWS + 1];
   __shared__ d2 part[2][NW][ROWS];
   __shared__ double wred[2][kThreads / 64];
-  if (a.check_stop && load_stopped(a.slot)) return;
+  static_assert(2 * CAP >= kFuseLds, "stop-test scratch");
+  if (iteration_stopped(a, reinterpret_cast<double*>(sval))) return;
 
   const int tid = threadIdx.x;
   const int lane = tid % ROWS, wv = tid / ROWS;  // row within the block, entry group
@@ -378,8 +403,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // memory-side cache (MALL) until the next pass over the matrix; the rest are
 // read non-temporally.
 template <int RPW, int MODE>
-__global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a,
+__global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a_in,
                                                                                       int keep_entries) {
+  const IterArgs a = resolve_args(a_in);
   constexpr int NWAVE = kThreads / 64;
   constexpr int G = 64 / RPW;      // entry groups per row
   constexpr int CAPW = RPW * 32;   // entries staged per chunk
@@ -391,8 +417,8 @@ __global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave
   __shared__ double wred[2][NWAVE];
   // The stop flag is the same for every wave of the launch; it is tested only
   // once the row pointers and own-row operands are in flight, so its latency
-  // overlaps theirs.
-  const int stopped = a.check_stop ? load_stopped(a.slot) : 0;
+  // overlaps theirs (the fused test reduces the partials first).
+  const bool stopped = iteration_stopped(a, reinterpret_cast<double*>(&sval[0][0]));
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -551,7 +577,8 @@ __global__ __launch_bounds__(kThreads, MODE == kLejaComm ? 6 : 7) void csr2_wave
 template <int RPW, int NT>
 __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1, const double2* H2,
                                                               int dim, long long ld, IterArgs a, int keep_rows) {
-  if (a.check_stop && load_stopped(a.slot)) return;
+  __shared__ double fz[kFuseLds];
+  if (iteration_stopped(a, fz)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int rbase = (L * (kThreads / 64) + wv) * RPW;
@@ -772,6 +799,9 @@ __global__ void copy_kernel(const double2* __restrict__ src, double2* __restrict
   if (i < n) dst[i] = src[i];
 }
 
+__global__ void step_set_kernel(int* ctr, int value) { *ctr = value; }
+__global__ void step_advance_kernel(int* ctr) { *ctr += 1; }
+
 __global__ void slot_reset_kernel(Slot* s, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -783,6 +813,8 @@ __global__ void slot_reset_kernel(Slot* s, int n) {
     s[i].vnorm = 0.0;
     s[i].prev_term = 0.0;
     s[i].last_est = 0.0;
+    s[i].term[0] = 0.0;
+    s[i].term[1] = 0.0;
   }
 }
 
@@ -858,11 +890,12 @@ hipError_t launch_dense_gershgorin(const double2* H, int dim, long long ld, doub
   return hipGetLastError();
 }
 
-// Rows per wave: 2 (with 8192 rows that is 16 waves per CU; more rows per
-// wave leave too few waves to cover the memory latency).
-constexpr int kDenseRPW2 = 2, kDenseRPW1 = 2;
-int dense2_grid(int dim, int nterms) {
-  const int rows_per_block = (nterms == 2 ? kDenseRPW2 : kDenseRPW1) * (kThreads / 64);
+// Rows per wave: 1, 2 or 4 (magnus_autotune times them on the caller's
+// terms; 2 by default: with 8192 rows that is 16 waves per CU, and more rows
+// per wave leave too few waves to cover the memory latency).
+int dense2_grid(int dim, int nterms, int rpw) {
+  (void)nterms;
+  const int rows_per_block = rpw * (kThreads / 64);
   return (dim + rows_per_block - 1) / rows_per_block;
 }
 
@@ -871,12 +904,23 @@ int dense2_grid(int dim, int nterms) {
 constexpr long long kDenseMallKeepBytes = 240LL << 20;
 
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
-                              const IterArgs& a, hipStream_t s) {
+                              const IterArgs& a, hipStream_t s, int rpw) {
   const long long row_bytes = 16LL * ld * (H2 ? 2 : 1);
   const long long keep = std::max(0LL, kDenseMallKeepBytes - 80LL * dim) / std::max(1LL, row_bytes);
   const int keep_rows = (int)std::min<long long>(keep, dim);
-  if (H2) dense2_iter_kernel<kDenseRPW2, 2><<<dense2_grid(dim, 2), kThreads, 0, s>>>(H1, H2, dim, ld, a, keep_rows);
-  else dense2_iter_kernel<kDenseRPW1, 1><<<dense2_grid(dim, 1), kThreads, 0, s>>>(H1, H1, dim, ld, a, keep_rows);
+  const int g = dense2_grid(dim, H2 ? 2 : 1, rpw);
+#define MAGNUS_DENSE_CASE(R)                                                             \
+  case R:                                                                                \
+    if (H2) dense2_iter_kernel<R, 2><<<g, kThreads, 0, s>>>(H1, H2, dim, ld, a, keep_rows); \
+    else dense2_iter_kernel<R, 1><<<g, kThreads, 0, s>>>(H1, H1, dim, ld, a, keep_rows);    \
+    break;
+  switch (rpw) {
+    MAGNUS_DENSE_CASE(1)
+    MAGNUS_DENSE_CASE(2)
+    MAGNUS_DENSE_CASE(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef MAGNUS_DENSE_CASE
   return hipGetLastError();
 }
 
@@ -903,8 +947,23 @@ hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_
   return hipGetLastError();
 }
 
+hipError_t launch_leja_final_check(const IterArgs& a, hipStream_t s) {
+  leja_final_check_kernel<<<1, kDecideThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 hipError_t launch_leja_decide(const IterArgs& a, int grid, hipStream_t s) {
   leja_decide_kernel<<<1, kDecideThreads, 0, s>>>(a, grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_set(int* ctr, int value, hipStream_t s) {
+  step_set_kernel<<<1, 1, 0, s>>>(ctr, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_advance(int* ctr, hipStream_t s) {
+  step_advance_kernel<<<1, 1, 0, s>>>(ctr);
   return hipGetLastError();
 }
 

@@ -112,8 +112,10 @@ __global__ __launch_bounds__(kCommWaves * 64) void csr_commutator_kernel(CsrDev 
 // ---------------------------------------------------------------------------
 constexpr int kRPW3 = 8;
 
-__global__ __launch_bounds__(kThreads, 5) void csr3_wave_kernel(CsrDev t1, CsrDev t2, CsrDev t3, int dim, IterArgs a,
-                                                               double a3, int keep_entries) {
+__global__ __launch_bounds__(kThreads, 5) void csr3_wave_kernel(CsrDev t1, CsrDev t2, CsrDev t3, int dim, IterArgs a_in,
+                                                               double a3_arg, int keep_entries) {
+  const IterArgs a = resolve_args(a_in);
+  const double a3 = a_in.coef ? a.kap : a3_arg;  // replayed: scale * kappa from the table
   constexpr int NWAVE = kThreads / 64;
   constexpr int RPW = kRPW3;
   constexpr int G = 64 / RPW;
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(kThreads, 5) void csr3_wave_kernel(CsrDev t1, CsrDe
   __shared__ int scol[NWAVE][CAPW];
   __shared__ int srp[NWAVE][3][RPW + 1];
   __shared__ double wred[2][NWAVE];
-  const int stopped = a.check_stop ? load_stopped(a.slot) : 0;
+  const bool stopped = iteration_stopped(a, reinterpret_cast<double*>(&sval[0][0]));
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
   const int row0 = (L * NWAVE + wv) * RPW;

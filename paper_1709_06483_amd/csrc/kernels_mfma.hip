@@ -7,9 +7,10 @@
 // NT = 1: one (assembled) matrix, y_b = a1_b (H w_b).
 // NT = 2: two terms with per-state coefficients folded into the W operand,
 //         y_b = H1 (a1_b w_b) + H2 (a2_b w_b).
-// A wave computes a 16 x 32 output tile (1 x 2 MFMA tiles), a workgroup of
-// four waves 32 rows x 64 states; K is staged through LDS 16 at a time with
-// the next chunk prefetched into registers while the MFMAs run.
+// Several tile shapes (kMfmaTiles, chosen per problem by magnus_autotune):
+// a wave computes TI x TJ MFMA tiles, four waves per K group a 32 TI x 32 TJ
+// block of rows x states; K is staged through LDS 16 at a time with the next
+// chunk prefetched into registers while the MFMAs run.
 #include <type_traits>
 
 #include "device_common.h"
@@ -20,21 +21,31 @@ namespace {
 using namespace dev;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 32, TN = 64, TK = 16;
-constexpr int WM = 16, WN = 32;   // wave tile
-constexpr int TJ = WN / 16;       // MFMA tiles per wave along the states
-// K is split between KS groups of four waves: group g accumulates the K
-// chunks g, g + KS, ... of the workgroup's tile in its own LDS slice, and the
-// groups' accumulators are added in a fixed order at the end.  A 32 x 64 tile
-// per workgroup leaves few workgroups for the chip (512 at 4096 rows and 256
-// states); the split gives each SIMD four waves to overlap the MFMA chains
-// with the staging of the next chunk.
-constexpr int KS = 2;
-constexpr int kMfmaThreads = KS * kThreads;
+constexpr int TK = 16;
 
-template <int NT>
-__global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const double2* H1, const double2* H2,
-                                                                      long long ld, int dim, MultiArgs a) {
+// Tile shape of one instantiation: a wave computes TI x TJ MFMA tiles of
+// 16 x 16 (16 TI rows, 16 TJ states), four waves per K group in a 2 x 2
+// arrangement make the workgroup tile TM x TN = 32 TI x 32 TJ, and K is
+// split between KS groups of four waves: group g accumulates the K chunks
+// g, g + KS, ... of the workgroup's tile in its own LDS slice, and the
+// groups' accumulators are added in a fixed order at the end.  Larger wave
+// tiles read fewer LDS operands per MFMA; the split gives each SIMD more
+// waves to overlap the MFMA chains with the staging of the next chunk.
+template <int TI_, int TJ_, int KS_>
+struct MfmaTile {
+  static constexpr int TI = TI_, TJ = TJ_, KS = KS_;
+  static constexpr int WM = 16 * TI, WN = 16 * TJ;
+  static constexpr int TM = 2 * WM, TN = 2 * WN;
+  static constexpr int THREADS = KS * kThreads;
+  static constexpr int HU = TM * TK / kThreads;  // H elements per thread and term (consecutive along K)
+  static constexpr int WU = TK * TN / kThreads;  // W elements per thread (consecutive states)
+};
+
+template <int NT, class T>
+__global__ __launch_bounds__(T::THREADS) void dense_mfma_leja_kernel(const double2* H1, const double2* H2,
+                                                                     long long ld, int dim, MultiArgs a) {
+  constexpr int TI = T::TI, TJ = T::TJ, KS = T::KS, WM = T::WM, WN = T::WN, TM = T::TM, TN = T::TN;
+  constexpr int HU = T::HU, WU = T::WU;
   __shared__ double sHre[KS][NT][TM][TK + 1], sHim[KS][NT][TM][TK + 1];
   __shared__ double sWre[KS][TK][TN + 1], sWim[KS][TK][TN + 1];
   __shared__ double csum[2][2][TN];  // [row half][w|v][state]
@@ -71,17 +82,18 @@ __global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const dou
     if constexpr (NT == 2) sc[1][tj] = P.a2;
   }
 
-  // staging assignment within the group: H tile TM x TK per term (2 complex
-  // per thread), W tile TK x TN (4 complex per thread)
-  const int h_r = gtid >> 3, h_k = (gtid & 7) * 2;        // 32 rows x 8 pairs
-  const int w_k = gtid >> 4, w_c = (gtid & 15) * 4;       // 16 k x 16 quads
+  // staging assignment within the group: the H tile TM x TK per term (HU
+  // consecutive K entries per thread), the W tile TK x TN (WU consecutive
+  // states per thread)
+  const int h_r = gtid / (TK / HU), h_k = (gtid % (TK / HU)) * HU;
+  const int w_k = gtid / (TN / WU), w_c = (gtid % (TN / WU)) * WU;
   const d2* W = reinterpret_cast<const d2*>(a.x);
   const d2* Hp[2] = {reinterpret_cast<const d2*>(H1), reinterpret_cast<const d2*>(H2)};
   // PD chunks of each group are in flight in registers (slot s holds the
-  // chunks of rounds s, s + PD, ...): two for one term, whose staging
-  // registers leave room for it, one for two terms
-  constexpr int PD = NT == 1 ? 2 : 1;
-  d2 hreg[PD][NT][2], wreg[PD][4];
+  // chunks of rounds s, s + PD, ...): two when the staging registers leave
+  // room for them (one term, small tiles), else one
+  constexpr int PD = (NT == 1 && HU + WU <= 6) ? 2 : 1;
+  d2 hreg[PD][NT][HU], wreg[PD][WU];
   // Loads without branches (every index clamped into the matrix), so the
   // compiler can count them and wait for one slot while the next is in
   // flight.  Rows past dim and states past B only reach outputs that are
@@ -92,12 +104,12 @@ __global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const dou
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < HU; ++u) {
         const int r = min(row0 + h_r, dim - 1), k = min(k0 + h_k + u, dim - 1);
         hreg[S][t][u] = __builtin_nontemporal_load(Hp[t] + (long long)r * ld + k);
       }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < WU; ++u) {
       const int k = min(k0 + w_k, dim - 1), c = min(col0 + w_c + u, B - 1);
       wreg[S][u] = W[(long long)k * B + c];
     }
@@ -108,23 +120,25 @@ __global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const dou
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < HU; ++u) {
         sHre[kg][t][h_r][h_k + u] = hreg[S][t][u].x;
         sHim[kg][t][h_r][h_k + u] = hreg[S][t][u].y;
       }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < WU; ++u) {
       sWre[kg][w_k][w_c + u] = k_in ? wreg[S][u].x : 0.0;
       sWim[kg][w_k][w_c + u] = k_in ? wreg[S][u].y : 0.0;
     }
   };
 
-  v4d are[TJ], aim[TJ];
+  v4d are[TI][TJ], aim[TI][TJ];
 #pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) {
-    are[tj] = v4d{0.0, 0.0, 0.0, 0.0};
-    aim[tj] = v4d{0.0, 0.0, 0.0, 0.0};
-  }
+  for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj) {
+      are[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+      aim[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
   const int nk = (dim + TK - 1) / TK;
   const int rounds = (nk + KS - 1) / KS;  // the same barrier count for every group
   // one round: stage this round's chunk from its slot, refill the slot with
@@ -140,29 +154,37 @@ __global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const dou
 #pragma unroll
     for (int ks = 0; ks < TK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
-      const int ar = wr * WM + (lane & 15);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const double hre = sHre[kg][t][ar][kk], him = sHim[kg][t][ar][kk];
-        double wre[TJ], wim[TJ];
+        double hre[TI], him[TI], wre[TJ], wim[TJ];
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti) {
+          const int ar = wr * WM + ti * 16 + (lane & 15);
+          hre[ti] = sHre[kg][t][ar][kk];
+          him[ti] = sHim[kg][t][ar][kk];
+        }
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj) {
           const int bc = wc * WN + tj * 16 + (lane & 15);
           wre[tj] = sWre[kg][kk][bc] * sc[t][tj];
           wim[tj] = sWim[kg][kk][bc] * sc[t][tj];
         }
-        // the 2 TJ accumulators are independent chains: issue one product into each
-        // before the second product of any, so dependent MFMAs are never back to back
+        // the 2 TI TJ accumulators are independent chains: issue one product into
+        // each before the second product of any, so dependent MFMAs are never back to back
 #pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) {
-          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wre[tj], are[tj], 0, 0, 0);
-          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre, wim[tj], aim[tj], 0, 0, 0);
-        }
+        for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) {
-          are[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-him, wim[tj], are[tj], 0, 0, 0);
-          aim[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(him, wre[tj], aim[tj], 0, 0, 0);
-        }
+          for (int tj = 0; tj < TJ; ++tj) {
+            are[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre[ti], wre[tj], are[ti][tj], 0, 0, 0);
+            aim[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(hre[ti], wim[tj], aim[ti][tj], 0, 0, 0);
+          }
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < TJ; ++tj) {
+            are[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-him[ti], wim[tj], are[ti][tj], 0, 0, 0);
+            aim[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(him[ti], wre[tj], aim[ti][tj], 0, 0, 0);
+          }
       }
     }
   };
@@ -177,34 +199,37 @@ __global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const dou
     for (int it = 0; it < rounds; ++it) round(std::integral_constant<int, 0>{}, it);
   }
 
-  // the groups' accumulators, added in group order: group g > 0 parks its
-  // values in the (now idle) W staging buffers, group 0 adds them
-  static_assert(sizeof(sWre) >= sizeof(double) * 4 * TJ * kThreads, "accumulator exchange space");
-  double* xre = &sWre[0][0][0];
-  double* xim = &sWim[0][0][0];
-  __syncthreads();  // every group's last chunk has been read
+  // the groups' accumulators, added in group order, one MFMA tile at a time:
+  // group g > 0 parks its values in the (now idle) W staging buffers, group 0
+  // adds them
+  if constexpr (KS > 1) {
+    static_assert(sizeof(sWre) >= sizeof(double) * 4 * kThreads, "accumulator exchange space");
+    double* xre = &sWre[0][0][0];
+    double* xim = &sWim[0][0][0];
+    __syncthreads();  // every group's last chunk has been read
 #pragma unroll
-  for (int g = 1; g < KS; ++g) {
-    if (kg == g) {
-#pragma unroll
-      for (int tj = 0; tj < TJ; ++tj)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          xre[(tj * 4 + j) * kThreads + gtid] = are[tj][j];
-          xim[(tj * 4 + j) * kThreads + gtid] = aim[tj][j];
-        }
-    }
-    __syncthreads();
-    if (kg == 0) {
+    for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
       for (int tj = 0; tj < TJ; ++tj)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          are[tj][j] += xre[(tj * 4 + j) * kThreads + gtid];
-          aim[tj][j] += xim[(tj * 4 + j) * kThreads + gtid];
+        for (int g = 1; g < KS; ++g) {
+          if (kg == g) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              xre[j * kThreads + gtid] = are[ti][tj][j];
+              xim[j * kThreads + gtid] = aim[ti][tj][j];
+            }
+          }
+          __syncthreads();
+          if (kg == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              are[ti][tj][j] += xre[j * kThreads + gtid];
+              aim[ti][tj][j] += xim[j * kThreads + gtid];
+            }
+          }
+          __syncthreads();
         }
-    }
-    __syncthreads();
   }
   const bool epi = kg == 0;  // group 0 holds the sums; the others only keep the barrier count
 
@@ -221,26 +246,28 @@ __global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const dou
     const bool stopped_c = a.check_stop ? load_stopped(&a.slots[c]) != 0 : false;
     const double ys = NT == 2 ? 1.0 : P.a1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = row0 + wr * WM + (lane >> 4) + 4 * j;
-      if (r >= dim) continue;
-      const long long idx = (long long)r * B + c;
-      const d2 y = d2{ys * are[tj][j], ys * aim[tj][j]};
-      const d2 w_old = W[idx];
-      const d2 wn = y - rmul(P.sigma, w_old);
-      const d2 dd = {P.dre, P.dim};
-      d2 p;
-      if (a.first) {
-        p = cmul(d2{P.d0re, P.d0im}, w_old) + cmul(dd, wn);
-        pv[tj] += nrm2(w_old);
-      } else {
-        p = tod2(a.pacc[idx]);
-        if (!stopped_c) p += cmul(dd, wn);
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + wr * WM + ti * 16 + (lane >> 4) + 4 * j;
+        if (r >= dim) continue;
+        const long long idx = (long long)r * B + c;
+        const d2 y = d2{ys * are[ti][tj][j], ys * aim[ti][tj][j]};
+        const d2 w_old = W[idx];
+        const d2 wn = y - rmul(P.sigma, w_old);
+        const d2 dd = {P.dre, P.dim};
+        d2 p;
+        if (a.first) {
+          p = cmul(d2{P.d0re, P.d0im}, w_old) + cmul(dd, wn);
+          pv[tj] += nrm2(w_old);
+        } else {
+          p = tod2(a.pacc[idx]);
+          if (!stopped_c) p += cmul(dd, wn);
+        }
+        a.wout[idx] = fromd2(wn);
+        a.pacc[idx] = fromd2(p);
+        pw[tj] += nrm2(wn);
       }
-      a.wout[idx] = fromd2(wn);
-      a.pacc[idx] = fromd2(p);
-      pw[tj] += nrm2(wn);
-    }
   }
   // per-state sums: lanes l, l + 16, l + 32, l + 48 share a state
 #pragma unroll
@@ -256,10 +283,16 @@ __global__ __launch_bounds__(kMfmaThreads) void dense_mfma_leja_kernel(const dou
   }
   __syncthreads();
   if (tid < TN && col0 + tid < B) {
-    // column-major (state, row block), as the decide kernel reads them
-    const long long o = ((long long)(col0 + tid) * (gridDim.x / gx) + rb) * 2;
+    // column-major (state, 32-row block), as the decide kernel reads them: a
+    // tile of TM rows writes its sums at its first 32-row block, zeros at the others
+    const int rb32 = row0 / 32, nrb32 = (dim + 31) / 32;
+    const long long o = ((long long)(col0 + tid) * nrb32 + rb32) * 2;
     a.partials[o] = csum[0][0][tid] + csum[1][0][tid];
     a.partials[o + 1] = csum[0][1][tid] + csum[1][1][tid];
+    for (int q = 1; q < TM / 32 && rb32 + q < nrb32; ++q) {
+      a.partials[o + 2 * q] = 0.0;
+      a.partials[o + 2 * q + 1] = 0.0;
+    }
   }
 }
 
@@ -283,15 +316,31 @@ __global__ void dense_assemble_kernel(const double2* __restrict__ H1, const doub
 
 }  // namespace
 
-int dense_mfma_row_blocks(int dim) { return (dim + TM - 1) / TM; }
+// Partial sums are kept per 32-row block whatever the tile's height.
+int dense_mfma_row_blocks(int dim) { return (dim + 31) / 32; }
+
+namespace {
+template <class T>
+hipError_t launch_mfma_tile(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
+                            const MultiArgs& a, hipStream_t s) {
+  const int gx = (a.B + T::TN - 1) / T::TN;
+  const int grid = (dim + T::TM - 1) / T::TM * gx;
+  if (nterms == 1) dense_mfma_leja_kernel<1, T><<<grid, T::THREADS, 0, s>>>(H1, H2, ld, dim, a);
+  else dense_mfma_leja_kernel<2, T><<<grid, T::THREADS, 0, s>>>(H1, H2, ld, dim, a);
+  return hipGetLastError();
+}
+}  // namespace
 
 hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
-                             const MultiArgs& a, hipStream_t s) {
-  const int gx = (a.B + TN - 1) / TN;
-  const int grid = dense_mfma_row_blocks(dim) * gx;
-  if (nterms == 1) dense_mfma_leja_kernel<1><<<grid, kMfmaThreads, 0, s>>>(H1, H2, ld, dim, a);
-  else dense_mfma_leja_kernel<2><<<grid, kMfmaThreads, 0, s>>>(H1, H2, ld, dim, a);
-  return hipGetLastError();
+                             const MultiArgs& a, hipStream_t s, int tile) {
+  switch (tile) {
+    case 0: return launch_mfma_tile<MfmaTile<1, 2, 2>>(nterms, H1, H2, ld, dim, a, s);  // 32 x 64, K split in two
+    case 1: return launch_mfma_tile<MfmaTile<1, 2, 1>>(nterms, H1, H2, ld, dim, a, s);  // 32 x 64
+    case 2: return launch_mfma_tile<MfmaTile<2, 2, 1>>(nterms, H1, H2, ld, dim, a, s);  // 64 x 64
+    case 3: return launch_mfma_tile<MfmaTile<2, 2, 2>>(nterms, H1, H2, ld, dim, a, s);  // 64 x 64, K split in two
+    case 4: return launch_mfma_tile<MfmaTile<1, 4, 2>>(nterms, H1, H2, ld, dim, a, s);  // 32 x 128, K split in two
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_dense_assemble(const double2* H1, const double2* H2, long long ld, int dim, double ca, double cb,

@@ -21,9 +21,12 @@ using namespace dev;
 // keep_entries: tiles whose entries start within the first keep_entries of the
 // two terms are read with normal loads (they stay in the MALL until the next
 // iteration), the rest non-temporally.
+//
+// The body takes the workgroup's block index bid among nb blocks of its
+// problem, so that one launch can serve several problems (ragged batches).
 template <int B, int MODE>
-__global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev t2, int dim, MultiArgs a,
-                                                             int keep_entries) {
+__device__ __forceinline__ void multi_body(const CsrDev& t1, const CsrDev& t2, int dim, const MultiArgs& a,
+                                           int keep_entries, int bid, int nb) {
   constexpr int NWAVE = kThreads / 64;
   constexpr int RP = 64 / B;                // rows per pass: lane = rr * B + b
   constexpr int RPW = RP;                   // rows per wave: one pass (with many states the
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev 
     for (int k = 0; k < B; ++k) all = all && sstop[k];
     if (all) return;  // uniform over the workgroup
   }
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int L = xcd_remap(bid, nb);
   const int row0 = (L * NWAVE + wv) * RPW;
   const int nrows = max(0, min(RPW, dim - row0));
   const int rr = lane / B, b = lane % B;
@@ -171,18 +174,34 @@ __global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev 
   if (tid < B) {
     double bw = 0.0, bv = 0.0;
     for (int w = 0; w < NWAVE; ++w) { bw += wsum[w][tid][0]; bv += wsum[w][tid][1]; }
-    // column-major (column tid, workgroup blockIdx.x), so each column's decide reads contiguously
-    a.partials[((long long)tid * gridDim.x + blockIdx.x) * 2] = bw;
-    a.partials[((long long)tid * gridDim.x + blockIdx.x) * 2 + 1] = bv;
+    // column-major (column tid, workgroup bid), so each column's decide reads contiguously
+    a.partials[((long long)tid * nb + bid) * 2] = bw;
+    a.partials[((long long)tid * nb + bid) * 2 + 1] = bv;
   }
+}
+
+template <int B, int MODE>
+__global__ __launch_bounds__(kThreads) void csr2_multi_kernel(CsrDev t1, CsrDev t2, int dim, MultiArgs a,
+                                                             int keep_entries) {
+  multi_body<B, MODE>(t1, t2, dim, a, keep_entries, blockIdx.x, gridDim.x);
+}
+
+// Several problems (own terms, states, coefficients, slots and partials) in
+// one launch: problem q owns blocks [block0[q], block0[q + 1]).
+template <int B>
+__global__ __launch_bounds__(kThreads) void csr2_ragged_kernel(RaggedArgs r) {
+  int q = 0;
+  while (q + 1 < r.np && (int)blockIdx.x >= r.p[q + 1].block0) ++q;  // uniform
+  const int nb = (q + 1 < r.np ? r.p[q + 1].block0 : (int)gridDim.x) - r.p[q].block0;
+  multi_body<B, kMultiLeja>(r.p[q].t1, r.p[q].t2, r.p[q].dim, r.p[q].a, r.p[q].keep_entries,
+                            (int)blockIdx.x - r.p[q].block0, nb);
 }
 
 // One workgroup per column (or one for the joint block vector): fixed-order
 // reduction over workgroups, then the stop verdict.
 constexpr int kDecideThreads = 1024;
-__global__ __launch_bounds__(kDecideThreads) void multi_decide_kernel(MultiArgs a, int grid) {
+__device__ __forceinline__ void multi_decide_body(const MultiArgs& a, int grid, int col) {
   __shared__ double red[2][kDecideThreads / 64];
-  const int col = blockIdx.x;
   Slot* S = &a.slots[col];
   if (a.check_stop && load_stopped(S)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -215,6 +234,19 @@ __global__ __launch_bounds__(kDecideThreads) void multi_decide_kernel(MultiArgs 
     if (a.joint)
       for (int c = 1; c < a.B; ++c) a.slots[c] = *S;
   }
+}
+
+__global__ __launch_bounds__(kDecideThreads) void multi_decide_kernel(MultiArgs a, int grid) {
+  multi_decide_body(a, grid, blockIdx.x);
+}
+
+// Column decisions of a ragged launch: workgroup col0[q] + c decides column c
+// of problem q over that problem's grid.
+__global__ __launch_bounds__(kDecideThreads) void ragged_decide_kernel(RaggedArgs r) {
+  int q = 0;
+  while (q + 1 < r.np && (int)blockIdx.x >= r.p[q + 1].col0) ++q;  // uniform
+  const int nb = (q + 1 < r.np ? r.p[q + 1].block0 : r.nblocks) - r.p[q].block0;
+  multi_decide_body(r.p[q].a, nb, (int)blockIdx.x - r.p[q].col0);
 }
 
 __global__ void pack_kernel(const double2* __restrict__ src, double2* __restrict__ dst, int dim, int B) {
@@ -429,6 +461,39 @@ hipError_t launch_csr2_multi(int mode, const CsrDev& t1, const CsrDev& t2, int d
 
 hipError_t launch_multi_decide(const MultiArgs& a, int grid, hipStream_t s) {
   multi_decide_kernel<<<a.joint ? 1 : a.B, kDecideThreads, 0, s>>>(a, grid);
+  return hipGetLastError();
+}
+
+int ragged_grid(int dim, int B) {
+  const int g = csr2_multi_grid(dim, B);
+  return (g + 7) / 8 * 8;  // whole rounds of the 8 XCDs, so the XCD-aware row order holds per problem
+}
+
+hipError_t launch_csr2_ragged(RaggedArgs r, int B, hipStream_t s) {
+  if (r.np < 1 || r.np > kMaxRagged) return hipErrorInvalidValue;
+  int blocks = 0, cols = 0;
+  for (int q = 0; q < r.np; ++q) {
+    if (r.p[q].a.B != B || r.p[q].a.joint) return hipErrorInvalidValue;
+    r.p[q].block0 = blocks;
+    r.p[q].col0 = cols;
+    // the MALL's 256 MiB less a margin and the vectors of all B states (per problem)
+    const long long keep = std::max(0LL, (240LL << 20) - 80LL * r.p[q].dim * B) / 20;
+    r.p[q].keep_entries = (int)std::min<long long>(keep, 1LL << 30);
+    blocks += ragged_grid(r.p[q].dim, B);
+    cols += B;
+  }
+  r.nblocks = blocks;
+  switch (B) {
+    case 2: csr2_ragged_kernel<2><<<blocks, kThreads, 0, s>>>(r); break;
+    case 4: csr2_ragged_kernel<4><<<blocks, kThreads, 0, s>>>(r); break;
+    case 8: csr2_ragged_kernel<8><<<blocks, kThreads, 0, s>>>(r); break;
+    case 16: csr2_ragged_kernel<16><<<blocks, kThreads, 0, s>>>(r); break;
+    case 32: csr2_ragged_kernel<32><<<blocks, kThreads, 0, s>>>(r); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  ragged_decide_kernel<<<cols, kDecideThreads, 0, s>>>(r);
   return hipGetLastError();
 }
 

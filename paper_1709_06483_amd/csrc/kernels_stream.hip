@@ -116,13 +116,15 @@ struct Tile {
 // pacc = a2 w - i k H1 w, so that the kLeja pass H1 wout + H2 pacc (a1 = a2 = 1)
 // is a1 H1 w + a2 H2 w + k i[H1, H2] w.
 template <int MODE>
-__global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a,
+__global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, CsrDev t2, int dim, IterArgs a_in,
                                                                   int keep_entries) {
   static_assert(MODE == kLeja || MODE == kSplitComm, "streamed modes");
+  const IterArgs a = resolve_args(a_in);
   __shared__ StreamLds sh;
   // the stop flag is the same for every wave; it is tested once the first
-  // row pointers are in flight
-  const int stopped = a.check_stop ? load_stopped(a.slot) : 0;
+  // row pointers are in flight (the fused test reduces the partials first,
+  // in LDS that the copies reuse afterwards)
+  const bool stopped = iteration_stopped(a, reinterpret_cast<double*>(&sh.val[0][0][0]));
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = xcd_remap(blockIdx.x, gridDim.x);

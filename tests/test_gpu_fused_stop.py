@@ -1,0 +1,136 @@
+"""The stop test fused into the iteration kernels (every workgroup of
+iteration i reduces iteration i-1's norm partials itself, Section 3's early
+termination) against the decide kernel launched after every iteration
+(MAGNUS_FUSE=0): the same iteration counts and the same states, on every
+kernel family that takes the fused test (nonzero streaming, wave tiles,
+streamed tiles, the two-pass commutator iteration, dense GEMV), with
+spectral enclosures widened so that early termination really cuts the a
+priori degree; and non-finite norms of a call's last iteration reported."""
+import numpy as np
+import pytest
+
+from oracle import magnus as mg
+from paper_1709_06483_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected only where a GPU exists
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1709_06483_amd import binding as B  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def widen(ham, factor):
+    for T in (ham.struct.H1, ham.struct.H2):
+        c, r = 0.5 * (T.lam_min + T.lam_max), 0.5 * (T.lam_max - T.lam_min)
+        T.lam_min, T.lam_max = c - factor * r, c + factor * r
+    ham.struct.k_min *= factor
+    ham.struct.k_max *= factor
+    return ham
+
+
+def run(monkeypatch, fuse, make, method, nsteps, tau, psi0, f, tol):
+    monkeypatch.setenv("MAGNUS_FUSE", str(fuse))
+    ctx = B.Context(max_dim=psi0.shape[0])
+    ham = widen(B.magnus_spectral_bounds(ctx, make()), 3.0)
+    psi = torch.from_numpy(psi0).cuda()
+    fn = np.vectorize(f)(B.magnus_quadrature_nodes(B.METHODS[method], 0.0, tau, nsteps))
+    _, st = B.propagate(ctx, ham, B.METHODS[method], tau, fn, psi, opts=B.leja_opts(tol), stats=True)
+    out = psi.cpu().numpy()
+    ctx.close()
+    return out, st
+
+
+@pytest.mark.parametrize("n", [13, 14, 18])
+@pytest.mark.parametrize("method", ["CF4", "M4"])
+def test_fused_stop_test_matches_decide_kernel_on_chains(monkeypatch, n, method):
+    H1, H2 = inputs.chain_terms(n)
+    psi0 = inputs.random_states(1 << n, seed=70 + n)
+    f = inputs.cos_field(2.0)
+    make = lambda: B.DeviceHamiltonian.from_csr(H1, H2)
+    got, sf = run(monkeypatch, 1, make, method, 3, 0.02, psi0, f, 1e-12)
+    ref, sd = run(monkeypatch, 0, make, method, 3, 0.02, psi0, f, 1e-12)
+    print(f"n={n} {method}: fused iters {sf['iters']}, decide-kernel iters {sd['iters']}, planned "
+          f"{sf['planned_iters']}, rel diff {rel(got, ref):.2e}", flush=True)
+    assert sf["iters"] == sd["iters"] and sf["planned_iters"] == sd["planned_iters"]
+    assert rel(got, ref) <= 1e-13
+    if n == 13:
+        oref = mg.propagate(method, mg.two_term(H1.to_scipy(), H2.to_scipy(), f), 0.02, 3, psi0, expm="taylor")
+        assert rel(got, oref) <= 50 * 1e-12 * 6
+
+
+def test_fused_stop_test_dense(monkeypatch):
+    N = 1500
+    H0 = inputs.powerlaw_hermitian(N, 1.5, 20)
+    V = inputs.powerlaw_hermitian(N, 1.5, 21)
+    psi0 = inputs.random_states(N, seed=22)
+    f = inputs.sin_field(1.0)
+    make = lambda: B.DeviceHamiltonian.from_dense(H0, V)
+    got, sf = run(monkeypatch, 1, make, "CF4", 3, 0.05, psi0, f, 1e-12)
+    ref, sd = run(monkeypatch, 0, make, "CF4", 3, 0.05, psi0, f, 1e-12)
+    assert sf["iters"] == sd["iters"]
+    assert rel(got, ref) <= 1e-13
+    oref = mg.propagate("CF4", mg.two_term(H0, V, f), 0.05, 3, psi0, expm="taylor")
+    assert rel(got, oref) <= 50 * 1e-12 * 6
+
+
+def eigen_chain(n, ctx):
+    """Chain with a z field and its all-up state e_0, an eigenvector of both
+    terms (eigenvalues Delta (n - 1) and n), with the enclosures' upper ends
+    set to those eigenvalues: for a positive field the exponent's enclosure
+    then ends at e_0's eigenvalue, the first Leja point, so w_1 = (X - xi_0) e_0
+    vanishes to rounding and early termination stops every substep after
+    its second iteration."""
+    H1, H2 = inputs.chain_terms(n, field_axis="z")
+    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    ham.struct.H1.lam_max = 0.5 * (n - 1)
+    ham.struct.H2.lam_max = float(n)
+    v = np.zeros(1 << n, dtype=np.complex128)
+    v[0] = 1.0
+    return H1, H2, ham, v
+
+
+@pytest.mark.parametrize("n", [13, 14, 18])
+def test_fused_stop_test_stops_early(monkeypatch, n):
+    out = {}
+    for fuse in (1, 0):
+        monkeypatch.setenv("MAGNUS_FUSE", str(fuse))
+        ctx = B.Context(max_dim=1 << n)
+        H1, H2, ham, v = eigen_chain(n, ctx)
+        psi = torch.from_numpy(v).cuda()
+        fn = np.ones((4, 2))
+        _, st = B.propagate(ctx, ham, B.CF4, 0.02, fn, psi, opts=B.leja_opts(1e-12), stats=True)
+        out[fuse] = (psi.cpu().numpy(), st)
+        ctx.close()
+    (g, sf), (l, sd) = out[1], out[0]
+    print(f"n={n}: iters fused {sf['iters']}, decide kernel {sd['iters']}, planned {sf['planned_iters']}", flush=True)
+    assert sf["iters"] == sd["iters"] == 2 * sf["exponentials"] < sf["planned_iters"]
+    assert rel(g, l) <= 1e-14
+    lam = 0.5 * (n - 1) + 1.0 * n  # H1 + f H2 on e_0 with f = 1 over the step (Cf4 is exact here)
+    exact = np.zeros_like(g)
+    exact[0] = np.exp(-1j * 0.02 * 4 * lam)
+    assert rel(g, exact) <= 1e-12
+
+
+def test_fused_nan_in_a_one_iteration_call_is_reported(monkeypatch):
+    # a step so short that the plan has one iteration: no later iteration reduces
+    # its partials, the check at the end of the call does
+    monkeypatch.setenv("MAGNUS_FUSE", "1")
+    H1, H2 = inputs.chain_terms(10)
+    ctx = B.Context(max_dim=1024)
+    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_csr(H1, H2))
+    x = inputs.random_states(1024, seed=2)
+    x[100] = np.nan
+    with pytest.raises(B.MagnusError) as e:
+        B.expmv_leja(ctx, ham, 1.0, 0.5, 0.0, 1e-7, torch.from_numpy(x).cuda(), opts=B.leja_opts(1e-6),
+                     stats=True)
+    assert e.value.code == B.ENAN
+    w, st = B.expmv_leja(ctx, ham, 1.0, 0.5, 0.0, 1e-7, torch.from_numpy(inputs.random_states(1024, seed=3)).cuda(),
+                         opts=B.leja_opts(1e-6), stats=True)
+    assert st["planned_iters"] == 1 and st["iters"] == 1
+    ctx.close()

@@ -414,6 +414,84 @@ def test_dense_batched_mfma_matches_oracle(reserve, per_state, N):
     c.close()
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("reserve", [True, False])
+def test_dense_mfma_tile_shapes_match_oracle(tile, reserve, monkeypatch):
+    """Every FP64-MFMA tile shape the autotuner chooses from (32 x 64 and 64 x 64
+    rows x states with and without the K split, 32 x 128 with it) on a ragged
+    dim and batch, one term (assembled) and two."""
+    monkeypatch.setenv("MAGNUS_MFMA_TILE", str(tile))
+    N, Bn, tau, nsteps = 300, 70, 0.005, 4
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=31)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=32)
+    c = B.Context(max_dim=N, max_batch=Bn)
+    if reserve:
+        c.reserve_dense(N)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(H0, V))
+    psi0 = inputs.random_states(N, seed=30, batch=Bn)
+    f = inputs.sin_field(1.0)
+    psi = dev(psi0)
+    c.timing(True)
+    B.propagate(c, ham, B.CF4, tau, _field_nodes("CF4", f, 0.0, tau, nsteps), psi,
+                opts=B.leja_opts(BUDGET, tol_mode=1))
+    assert c.timing_read(B.KERNEL_DENSE_MFMA)[1] > 0
+    c.timing(False)
+    out = host(psi)
+    for k in (0, 37, Bn - 1):
+        ref = mg.propagate("CF4", mg.two_term(H0, V, f), tau, nsteps, psi0[k], expm="eig")
+        assert rel(out[k], ref) <= BUDGET, k
+    c.close()
+
+
+@pytest.mark.parametrize("rpw", [1, 2, 4])
+def test_dense_gemv_rows_per_wave_match_oracle(rpw, monkeypatch):
+    monkeypatch.setenv("MAGNUS_DENSE_RPW", str(rpw))
+    N, tau, nsteps = 1001, 0.005, 6
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=20)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=21)
+    c = B.Context(max_dim=N)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(H0, V))
+    f = inputs.sin_field(1.0)
+    psi0 = inputs.random_states(N, seed=22)
+    ref = mg.propagate("CF4", mg.two_term(H0, V, f), tau, nsteps, psi0, expm="eig")
+    for reserve in (False, True):  # two terms, then the assembled exponent
+        if reserve:
+            c.reserve_dense(N)
+        psi = dev(psi0)
+        B.propagate(c, ham, B.CF4, tau, _field_nodes("CF4", f, 0.0, tau, nsteps), psi,
+                    opts=B.leja_opts(BUDGET, tol_mode=1))
+        assert rel(host(psi), ref) <= BUDGET
+    c.close()
+
+
+def test_dense_autotune_choices_are_used_and_match_oracle():
+    N, Bn, tau, nsteps = 700, 40, 0.005, 4
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=31)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=32)
+    c = B.Context(max_dim=N, max_batch=Bn)
+    c.reserve_dense(N)
+    ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(H0, V))
+    res = B.magnus_autotune(c, ham, batch=Bn)
+    assert res["rows_per_wave"] in (1, 2, 4) and res["mfma_tile"] in B.MFMA_TILES
+    assert all(v > 0 for v in res["rows_per_wave_us"].values())
+    assert all(v is not None and v > 0 for v in res["mfma_tile_us"].values())
+    psi0 = inputs.random_states(N, seed=30, batch=Bn)
+    f = inputs.sin_field(1.0)
+    psi = dev(psi0)
+    B.propagate(c, ham, B.CF4, tau, _field_nodes("CF4", f, 0.0, tau, nsteps), psi,
+                opts=B.leja_opts(BUDGET, tol_mode=1))
+    one = dev(psi0[5])
+    B.propagate(c, ham, B.CF4, tau, _field_nodes("CF4", f, 0.0, tau, nsteps), one,
+                opts=B.leja_opts(BUDGET, tol_mode=1))
+    out = host(psi)
+    for k in (0, Bn - 1):
+        ref = mg.propagate("CF4", mg.two_term(H0, V, f), tau, nsteps, psi0[k], expm="eig")
+        assert rel(out[k], ref) <= BUDGET
+    ref5 = mg.propagate("CF4", mg.two_term(H0, V, f), tau, nsteps, psi0[5], expm="eig")
+    assert rel(host(one), ref5) <= BUDGET
+    c.close()
+
+
 @pytest.mark.parametrize("persist", ["1", "0"])
 def test_small_state_propagation_paths_agree(persist, monkeypatch):
     """Small states run whole propagations in one workgroup each (MAGNUS_PERSIST=1)
@@ -473,6 +551,46 @@ def test_ragged_batch_matches_oracle(persist, monkeypatch):
     c.close()
 
 
+def test_ragged_large_problems_in_one_launch_per_iteration(monkeypatch):
+    """Chains of 13, 14 and 15 spins with 4 states each (and a 10-spin chain
+    in the persistent launch), one call: with a workspace that holds all
+    large problems at once they advance together, one launch per Leja
+    iteration (MAGNUS_RAGGED_JOINT=1), else one after another (0); both
+    against the oracle, the same states either way, fewer launches jointly."""
+    tau, nsteps, per = 0.01, 8, 4
+    sizes = (10, 13, 14, 15)
+    runs = {}
+    for joint in ("1", "0"):
+        monkeypatch.setenv("MAGNUS_RAGGED_JOINT", joint)
+        c = B.Context(max_dim=sum(1 << n for n in sizes), max_batch=per)
+        probs, refs = [], []
+        for n in sizes:
+            H1, H2 = chain(n)
+            ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+            psi0 = inputs.random_states(1 << n, seed=400 + n, batch=per)
+            fields = [inputs.cos_field(2.0, 1.0 + k / 4) for k in range(per)]
+            fn = np.stack([_field_nodes("CF4", f, 0.0, tau, nsteps) for f in fields])
+            probs.append((ham, dev(psi0), fn))
+            refs.append((H1, H2, fields, psi0))
+        c.timing(True)
+        st = B.magnus_propagate_ragged(c, probs, B.CF4, tau, opts=B.leja_opts(BUDGET, tol_mode=1), stats=True)
+        _, launches = c.timing_read(B.KERNEL_CSR_MULTI)
+        c.timing(False)
+        runs[joint] = ([host(psi) for _, psi, _ in probs], st, launches)
+        c.close()
+    (outs, st, lj), (outs0, st0, l0) = runs["1"], runs["0"]
+    print(f"ragged 13/14/15 x 4: multi-state launches joint {lj}, one problem after another {l0}", flush=True)
+    assert 0 < lj < l0
+    assert st["exponentials"] == st0["exponentials"] == 2 * nsteps * per * len(sizes)
+    assert st["iters"] == st0["iters"]
+    for out, out0, (H1, H2, fields, psi0) in zip(outs, outs0, refs):
+        assert rel(out, out0) <= 1e-14
+        for k in (0, per - 1):
+            P = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[k])
+            ref = mg.propagate("CF4", P, tau, nsteps, psi0[k], expm="taylor")
+            assert rel(out[k], ref) <= BUDGET
+
+
 def test_autotune_choices_are_used_and_match_oracle():
     """The autotuner times every CSR row mapping and multi-state group size on the
     n = 13 chain, keeps the fastest, and later calls with those kernels still match
@@ -498,9 +616,6 @@ def test_autotune_choices_are_used_and_match_oracle():
     one = dev(psi0[2])
     B.propagate(c, ham, B.CF4, tau, fn, one, opts=B.leja_opts(BUDGET, tol_mode=1))
     assert rel(host(one), mg.propagate("CF4", P, tau, nsteps, psi0[2], expm="taylor")) <= BUDGET
-    with pytest.raises(B.MagnusError):
-        B.magnus_autotune(c, B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_dense(
-            inputs.powerlaw_hermitian(64, 1.5, 1), inputs.powerlaw_hermitian(64, 1.5, 2))))
     c.close()
 
 
