@@ -387,6 +387,8 @@ def other_workload(name: str, args, emit: bool = True):
             it_bytes = 32 * dim * dim + 64 * dim
         ctx = B.Context(max_dim=dim)
         ham = B.magnus_spectral_bounds(ctx, mk(ctx))
+        if name == "dense_8192" and not args.no_autotune:
+            line["autotune"] = B.magnus_autotune(ctx, ham)
         tau, nrun = cfg["tau"], cfg["nsteps"]
         tol_e = cfg["budget_tol"] / (2 * nrun)
         psi0 = inputs.random_states(dim, seed=cfg["psi_seed"] if "psi_seed" in cfg else cfg["seeds"]["psi"])
@@ -439,6 +441,11 @@ def other_workload(name: str, args, emit: bool = True):
         ctx = B.Context(max_dim=N, max_batch=Bn)
         ctx.reserve_dense(N)
         ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H0, V))
+        if not args.no_autotune:
+            line["autotune"] = B.magnus_autotune(ctx, ham, batch=Bn)
+            print(f"[bench] autotune: MFMA tile {line['autotune']['mfma_tile_name']} "
+                  f"({', '.join(f'{k}: {v:.1f} us' for k, v in line['autotune']['mfma_tile_us'].items())})",
+                  file=sys.stderr, flush=True)
         psi = torch.from_numpy(inputs.random_states(N, seed=cfg["seeds"]["psi"], batch=Bn)).cuda()
         f = inputs.sin_field(cfg["omega"])
         fn = np.vectorize(f)(B.magnus_quadrature_nodes(B.CF4, 0.0, tau, W + K))
