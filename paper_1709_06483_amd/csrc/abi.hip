@@ -504,11 +504,12 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
     CsrDev t3{ctx->kc_rp, ctx->kc_ci, ctx->kc_val};
     a.x1 = win;
     a.x2 = win;
-    const int grid = magnus::csr3_grid(dim);
+    const bool streamed = rpb == magnus::kStreamTile;  // the three-term kernel follows the two-term choice
+    const int grid = magnus::csr3_grid(dim, streamed);
     if (int rc = setup_stop_test(ctx, P, i, grid, &a, s)) return rc;
     const bool fused = a.fused;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_LEJA3, s,
-                  [&] { return magnus::launch_csr3_iter(t1, t2, t3, dim, a, P.scale * op.kappa, s); }));
+                  [&] { return magnus::launch_csr3_iter(t1, t2, t3, dim, a, P.scale * op.kappa, streamed, s); }));
     if (!fused) HIP_TRY(magnus::launch_leja_decide(a, grid, s));
     return MAGNUS_OK;
   }
@@ -1345,7 +1346,7 @@ bool graph_eligible(magnus_ctx* ctx, const magnus_hamiltonian* h, const magnus::
   const int dim = (int)h->H1.dim;
   const int rpb = rows_per_block(ctx, h);
   int grid = magnus::csr2_grid(dim, rpb);
-  if (S.commutator && csr_comm_ready(ctx, h)) grid = magnus::csr3_grid(dim);
+  if (S.commutator && csr_comm_ready(ctx, h)) grid = magnus::csr3_grid(dim, rpb == magnus::kStreamTile);
   return grid <= magnus::kFuseMaxGrid;
 }
 

@@ -303,9 +303,13 @@ constexpr int kCommCap = 1024;
 hipError_t launch_csr_commutator(bool fill, const CsrDev& A, const CsrDev& Bm, int dim, int* counts,
                                  const int* rp_out, int* ci_out, double2* val_out, int* overflow, hipStream_t s);
 // One Leja iteration on a1 H1 + a2 H2 + a3 K (kLeja semantics, x = a.x1).
-int csr3_grid(int dim);
+// streamed: the three-term kernel streamed through LDS like kStreamTile (grid
+// csr2_stream_grid), else the 8-row wave tiles.
+int csr3_grid(int dim, bool streamed);
 hipError_t launch_csr3_iter(const CsrDev& t1, const CsrDev& t2, const CsrDev& t3, int dim, const IterArgs& a,
-                            double a3, hipStream_t s);
+                            double a3, bool streamed, hipStream_t s);
+hipError_t launch_csr3_stream(const CsrDev& t1, const CsrDev& t2, const CsrDev& t3, int dim, const IterArgs& a,
+                              double a3, hipStream_t s);
 
 // ---- whole propagations in one workgroup per state (small dimensions) ----
 

@@ -10,7 +10,9 @@
 //
 // Iteration: the wave-tile mapping of the two-term kernel (8 rows per wave,
 // 8 lanes per row, each tile's entries of the three terms staged in LDS
-// with coalesced non-temporal loads, fixed-order shuffle sums).
+// with coalesced non-temporal loads, fixed-order shuffle sums).  Large
+// matrices take the streamed three-term kernel instead (LDS-DMA copies one
+// chunk ahead), which sums in the same order.
 #include <climits>
 #include <type_traits>
 
@@ -268,14 +270,16 @@ hipError_t launch_csr_commutator(bool fill, const CsrDev& A, const CsrDev& Bm, i
   return hipGetLastError();
 }
 
-int csr3_grid(int dim) {
+int csr3_grid(int dim, bool streamed) {
+  if (streamed) return csr2_stream_grid(dim);
   const int rows = kRPW3 * (kThreads / 64);
   return (dim + rows - 1) / rows;
 }
 
 hipError_t launch_csr3_iter(const CsrDev& t1, const CsrDev& t2, const CsrDev& t3, int dim, const IterArgs& a,
-                            double a3, hipStream_t s) {
-  csr3_wave_kernel<<<csr3_grid(dim), kThreads, 0, s>>>(t1, t2, t3, dim, a, a3, csr_keep_entries(dim));
+                            double a3, bool streamed, hipStream_t s) {
+  if (streamed) return launch_csr3_stream(t1, t2, t3, dim, a, a3, s);
+  csr3_wave_kernel<<<csr3_grid(dim, false), kThreads, 0, s>>>(t1, t2, t3, dim, a, a3, csr_keep_entries(dim));
   return hipGetLastError();
 }
 

@@ -4,7 +4,9 @@ matrix-free two-pass commutator."""
 import numpy as np
 import pytest
 
+from oracle import expm as oe
 from oracle import magnus as mg
+from oracle.linop import Comm, Lin, Mat
 from paper_1709_06483_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -47,8 +49,8 @@ def _random_sparse_hermitian(N, density, seed):
 @pytest.mark.parametrize("variant", ["0", "7"])
 @pytest.mark.parametrize("kind", ["chain", "random"])
 def test_assembled_commutator_m4_matches_oracle_and_matrix_free(kind, variant, monkeypatch):
-    """variant "0" is the size rule at these sizes; "7" forces the streamed two-term
-    tiles, under which the three-term pass takes the 8-row wave tiles."""
+    """variant "0" is the size rule at these sizes (the three-term pass takes the
+    8-row wave tiles); "7" forces the streamed tiles, for the three-term pass too."""
     monkeypatch.setenv("MAGNUS_CSR_VARIANT", variant)
     if kind == "chain":
         H1, H2 = inputs.chain_terms(10)
@@ -92,6 +94,51 @@ def test_assembled_commutator_m4_matches_oracle_and_matrix_free(kind, variant, m
     refw = Q @ (np.exp(-1j * lamO) * (Q.conj().T @ psi0))
     assert rel(host(w), refw) <= 1e-9
     c.close()
+
+
+def _ragged_csr(N, seed, per_row=6, empty_every=0):
+    """Random Hermitian CSR of N rows (about 2 per_row entries a row), some rows
+    empty when empty_every > 0."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, per_row + 1, size=N)
+    if empty_every:
+        lens[::empty_every] = 0
+    rows = np.repeat(np.arange(N), lens)
+    cols = rng.integers(0, N, size=rows.shape[0])
+    vals = rng.standard_normal(rows.shape[0]) + 1j * rng.standard_normal(rows.shape[0])
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+    H = (A + A.conj().T) * 0.5
+    return inputs.CSR.from_scipy(H), H
+
+
+@pytest.mark.parametrize("N", [1, 3, 17, 130, 5000, 300001])
+def test_streamed_three_term_kernel_matches_wave_tiles_and_oracle(N, monkeypatch):
+    """The streamed three-term kernel (H1, H2 and the assembled K in one entry
+    stream per tile) against the 8-row three-term wave tiles, which sum in the same
+    order, and against the oracle: dimensions that leave most tiles of a workgroup
+    empty, rows without entries in some terms, and a large ragged matrix whose
+    entries pass the memory-side-cache budget (normal and non-temporal loads)."""
+    H1, S1 = _ragged_csr(N, 2200 + N % 97, empty_every=7)
+    H2, S2 = _ragged_csr(N, 2300 + N % 89)
+    v = inputs.random_states(N, seed=2400 + N % 83)
+    tol = 1e-12
+    out = {}
+    for var in ("7", "5"):
+        monkeypatch.setenv("MAGNUS_CSR_VARIANT", var)
+        c = B.Context(max_dim=N, max_batch=1)
+        ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+        B.magnus_csr_commutator(c, ham)
+        c.timing(True)
+        out[var] = host(B.expmv_leja(c, ham, 0.7, -0.3, 0.02, 0.05, dev(v), opts=B.leja_opts(tol)))
+        assert c.timing_read(B.KERNEL_CSR_LEJA3)[1] > 0  # the three-term pass ran
+        c.timing(False)
+        c.close()
+    M1, M2 = Mat(S1), Mat(S2)
+    Om = Lin([(-1j * 0.05 * 0.7, M1), (-1j * 0.05 * -0.3, M2), (-1j * 0.05 * 0.02 * 1j, Comm(M1, M2))])
+    ref = oe.expmv_taylor(Om, v)
+    assert rel(out["7"], ref) <= 20 * tol + 1e-13, N
+    assert rel(out["7"], out["5"]) <= 1e-14, N
 
 
 def test_commutator_row_capacity_is_enforced():

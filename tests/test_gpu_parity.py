@@ -825,6 +825,30 @@ def test_streamed_tiles_small_and_degenerate(N, variant, monkeypatch):
     assert rel(w, ref) <= 20 * tol, N
 
 
+def test_streamed_tiles_large_ragged(monkeypatch):
+    """The streamed kernel on a large irregular matrix (over 2,000 blocks of 256
+    rows, the last one ragged, with empty rows and rows longer than two LDS chunks):
+    it matches the oracle and the 8-row wave-tile kernel, which sums in the same
+    order, in the Leja pass and in the two-pass matrix-free commutator."""
+    N = 2 * 1024 * 256 + 12345
+    H1 = _ragged_hermitian(N, 2101, long_rows=(7, N - 3), long_len=700)
+    H2 = _ragged_hermitian(N, 2102)
+    v = inputs.random_states(N, seed=2103)
+    tol = 1e-12
+    S1, S2 = H1.to_scipy(), H2.to_scipy()
+    for kappa in (0.0, 1e-4):
+        out = {}
+        for var in ("7", "5"):
+            monkeypatch.setenv("MAGNUS_CSR_VARIANT", var)
+            c = B.Context(max_dim=N)
+            ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+            out[var] = host(B.expmv_leja(c, ham, 0.6, -0.4, kappa, 0.01, dev(v), opts=B.leja_opts(tol)))
+            c.close()
+        ref = oe.expmv_taylor(oracle_exponent(S1, S2, 0.6, -0.4, kappa, 0.01), v)
+        assert rel(out["7"], ref) <= 20 * tol, kappa
+        assert rel(out["7"], out["5"]) <= 1e-14, kappa
+
+
 @pytest.mark.parametrize("stride", [1, 3])
 def test_kernel_timing_stride(stride):
     """magnus_timing with stride k brackets every k-th launch of a kernel class: the
