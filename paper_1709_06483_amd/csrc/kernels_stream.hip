@@ -7,10 +7,11 @@
 // values (term 1's entries of its rows, then term 2's) travel from HBM
 // straight into a wave-private LDS buffer with global_load_lds (no VGPRs held
 // while in flight), one chunk of 256 entries ahead of the chunk being
-// processed.  Per chunk the wave waits once: the copy of the chunk, issued
-// during the previous one, and the row pointers two tiles ahead have arrived;
-// it then reads its entries' columns, issues the gathers, issues the copy of
-// the next chunk behind them, and multiplies.  Lanes are laid out row-fastest
+// processed.  Per chunk the wave waits at the top: the copy of the chunk,
+// issued during the previous one, and the row pointers two tiles ahead have
+// arrived; it then reads its entries' columns, issues the gathers, issues the
+// copy of the next chunk behind them, and waits for both before it
+// multiplies.  Lanes are laid out row-fastest
 // (lane = g * 8 + r) and each row's 8 groups are summed with shuffles in a
 // fixed order, the same order and chunking as the 8-row wave-tile kernel.
 //
@@ -262,8 +263,11 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
             g1[i] = x1[b1 + i * kSG < end1 ? c1[i] : 0];
             g2[i] = x2[b2 + i * kSG < end2 ? c2[i] : 0];
           }
-          // the next chunk's copy goes out behind this round's gathers, so
-          // waiting for the gathers does not wait for it
+          // the next chunk's copy goes out behind this round's gathers.  The
+          // compiler's wait for the gathers waits for it too (it does not count
+          // copies into LDS apart from other loads), but in this order the
+          // gathers are served first; issued before them, the copy delays the
+          // gathers (n = 20: 200 us per iteration against 148)
           if (!issued) issue_next();
           d2 h1[kNB], h2[kNB];
           {
