@@ -132,9 +132,10 @@ struct magnus_ctx {
   std::set<std::tuple<const void*, const void*, const void*, int64_t, int64_t>> validated;
   std::mutex mu;
   // kernel timing: (kind, start, stop) per recorded launch, events reused from a pool
-  int csr_variant = 0;  // MAGNUS_CSR_VARIANT: 0 auto (wave tiles of 8 rows from 65536 rows on, streamed
-                        // wave tiles from 262144), 1 nonzero-streaming, 2-4 row-per-lane (64/32/128 rows),
-                        // 5-6 wave tiles (8/16 rows), 7 streamed wave tiles
+  int csr_variant = 0;  // MAGNUS_CSR_VARIANT: 0 auto (row per lane in blocks of 32 rows, of 64 from
+                        // 32768 rows, wave tiles of 16 rows from 65536, streamed wave tiles from 131072),
+                        // 1 nonzero-streaming, 2-4 row-per-lane (64/32/128 rows), 5-6 wave tiles
+                        // (8/16 rows), 7 streamed wave tiles
   // magnus_autotune results, per CSR term pair (H1 row_ptr, dim): the variant code
   // of the single-state iteration and the states per multi-state pass
   std::map<std::pair<const void*, int64_t>, int> tuned_variant, tuned_group;
@@ -315,10 +316,19 @@ int variant_rows(int code, int64_t dim) {
     case 5: return magnus::kWaveTile + 8;
     case 6: return magnus::kWaveTile + 16;
     case 7: return magnus::kStreamTile;
-    // measured on spin chains: the streamed tiles win from 2^18 rows on (n = 18:
-    // 42 vs 48 us, n = 20: 169 vs 183 us) and lose below 2^17, where the grid
-    // leaves compute units idle while each wave walks its 8 tiles in turn
-    default: return dim >= 262144 ? magnus::kStreamTile : dim >= 65536 ? magnus::kWaveTile + 8 : 16;
+    // Measured on spin chains, Cf4 steps/s with each mapping (the stop test is
+    // fused into the iteration on grids of at most kFuseMaxGrid workgroups, else
+    // a decide kernel follows every iteration): the streamed tiles from 2^17
+    // rows on (n = 17: 2,566 against 2,378 with 8-row wave tiles; n = 18, 19,
+    // 20: 42 vs 48 us and 169 vs 183 us per iteration), 16-row wave tiles at
+    // 2^16 (3,796 against 3,730), a row per lane in blocks of 64 rows at 2^15
+    // (8,134 against 4,922 with 16-row nonzero streaming) and of 32 rows
+    // below (n = 14: 9,183 against 7,585; n = 13: 9,983 against 9,657).
+    default:
+      return dim >= 131072 ? magnus::kStreamTile
+             : dim >= 65536 ? magnus::kWaveTile + 16
+             : dim >= 32768 ? -64
+                            : -32;
   }
 }
 

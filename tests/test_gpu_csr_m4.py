@@ -49,8 +49,9 @@ def _random_sparse_hermitian(N, density, seed):
 @pytest.mark.parametrize("variant", ["0", "7"])
 @pytest.mark.parametrize("kind", ["chain", "random"])
 def test_assembled_commutator_m4_matches_oracle_and_matrix_free(kind, variant, monkeypatch):
-    """variant "0" is the size rule at these sizes (the three-term pass takes the
-    8-row wave tiles); "7" forces the streamed tiles, for the three-term pass too."""
+    """variant "0" is the size rule at these sizes (a row per lane for the two-term
+    passes, the 8-row three-term wave tiles); "7" forces the streamed tiles, for the
+    three-term pass too."""
     monkeypatch.setenv("MAGNUS_CSR_VARIANT", variant)
     if kind == "chain":
         H1, H2 = inputs.chain_terms(10)

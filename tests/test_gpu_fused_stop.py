@@ -2,8 +2,8 @@
 iteration i reduces iteration i-1's norm partials itself, Section 3's early
 termination) against the decide kernel launched after every iteration
 (MAGNUS_FUSE=0): the same iteration counts and the same states, on every
-kernel family that takes the fused test (nonzero streaming, wave tiles,
-streamed tiles, the two-pass commutator iteration, dense GEMV), with
+kernel family that takes the fused test (row per lane, nonzero streaming,
+wave tiles, streamed tiles, the two-pass commutator iteration, dense GEMV), with
 spectral enclosures widened so that early termination really cuts the a
 priori degree; and non-finite norms of a call's last iteration reported."""
 import numpy as np
@@ -46,9 +46,13 @@ def run(monkeypatch, fuse, make, method, nsteps, tau, psi0, f, tol):
     return out, st
 
 
-@pytest.mark.parametrize("n", [13, 14, 18])
+# the mapping each size takes by default (n = 13 a row per lane in blocks of 32
+# rows, 15 of 64, 16 wave tiles of 16 rows, 17 and 18 streamed tiles), and the
+# 16-row nonzero streaming kernel forced at n = 14
+@pytest.mark.parametrize("n,variant", [(13, "0"), (14, "1"), (15, "0"), (16, "0"), (17, "0"), (18, "0")])
 @pytest.mark.parametrize("method", ["CF4", "M4"])
-def test_fused_stop_test_matches_decide_kernel_on_chains(monkeypatch, n, method):
+def test_fused_stop_test_matches_decide_kernel_on_chains(monkeypatch, n, variant, method):
+    monkeypatch.setenv("MAGNUS_CSR_VARIANT", variant)
     H1, H2 = inputs.chain_terms(n)
     psi0 = inputs.random_states(1 << n, seed=70 + n)
     f = inputs.cos_field(2.0)
