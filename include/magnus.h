@@ -425,7 +425,10 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
  * variable, when set, still wins.  Overwrites the context's work vectors.
  *   variant, group       HOST out (may be NULL): the chosen code and group size
  *   variant_us[7], group_us[5]  HOST out (may be NULL): measured microseconds per
- *                        launch (group entries NAN where not tried).
+ *                        iteration (a mapping whose grid is too large for the
+ *                        stop test fused into the iteration is timed with the
+ *                        decide kernel that then follows each iteration; group
+ *                        entries NAN where not tried).
  * Dense terms: times the two-term GEMV iteration with 1, 2 and 4 rows per
  * wave and, when batch > 1, the FP64-MFMA group iteration of batch states
  * with each tile shape (0: 32 rows x 64 states with K split between two

@@ -2010,7 +2010,16 @@ int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch,
   for (int code = 1; code <= kTuneVariants && err == hipSuccess; ++code) {
     const int rpb = variant_rows(code, dim);
     double us = 0.0;
-    err = time_us([&] { return magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s); }, &us);
+    // an iteration on a grid too large for the fused stop test is followed by
+    // the decide kernel, so that is timed with it
+    const bool decide = !ctx->fuse || magnus::csr2_grid(dim, rpb) > magnus::kFuseMaxGrid;
+    err = time_us(
+        [&] {
+          hipError_t e = magnus::launch_csr2_iter(magnus::kLeja, t1, t2, dim, a, rpb, s);
+          if (e == hipSuccess && decide) e = magnus::launch_leja_decide(a, magnus::csr2_grid(dim, rpb), s);
+          return e;
+        },
+        &us);
     if (variant_us) variant_us[code - 1] = us;
     if (us < best) {
       best = us;
