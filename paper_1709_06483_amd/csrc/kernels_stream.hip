@@ -319,29 +319,33 @@ __global__ __launch_bounds__(kThreads, 4) void csr2_stream_kernel(CsrDev t1, Csr
     rp_nxt = rp_after;
     T = Tn;
   }
+  // The norm partials go through LDS first, then the rows' results: any wait
+  // before an LDS access waits for every outstanding store too, and stores
+  // still in flight when the wave ends need no wait.
+  wait_vmem();  // no copy into this wave's buffers is still in flight
+  if (MODE == kLeja) {
+    pw = wave_sum(pw);
+    pv = wave_sum(pv);
+    double* red = reinterpret_cast<double*>(&sh.val[wv][0][0]);  // this wave's own buffer
+    if (lane == 0) {
+      red[0] = pw;
+      red[1] = pv;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double bw = 0.0, bv = 0.0;
+      for (int k = 0; k < kSW; ++k) {
+        const double* rk = reinterpret_cast<const double*>(&sh.val[k][0][0]);
+        bw += rk[0];
+        bv += rk[1];
+      }
+      a.partials[blockIdx.x] = bw;
+      if (a.first) a.partials[gridDim.x + blockIdx.x] = bv;
+    }
+  }
   if (my_valid) {
     a.wout[my_row] = fromd2(res_w);
     a.pacc[my_row] = fromd2(res_p);
-  }
-  wait_vmem();  // no copy into this wave's buffers is still in flight
-  if (MODE != kLeja) return;
-  pw = wave_sum(pw);
-  pv = wave_sum(pv);
-  double* red = reinterpret_cast<double*>(&sh.val[wv][0][0]);  // this wave's own buffer
-  if (lane == 0) {
-    red[0] = pw;
-    red[1] = pv;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double bw = 0.0, bv = 0.0;
-    for (int k = 0; k < kSW; ++k) {
-      const double* rk = reinterpret_cast<const double*>(&sh.val[k][0][0]);
-      bw += rk[0];
-      bv += rk[1];
-    }
-    a.partials[blockIdx.x] = bw;
-    if (a.first) a.partials[gridDim.x + blockIdx.x] = bv;
   }
 }
 
@@ -586,10 +590,7 @@ __global__ __launch_bounds__(kThreads, 4) void csr3_stream_kernel(CsrDev t1, Csr
     rp_nxt = rp_after;
     T = Tn;
   }
-  if (my_valid) {
-    a.wout[my_row] = fromd2(res_w);
-    a.pacc[my_row] = fromd2(res_p);
-  }
+  // partials first, then the rows' results (as in the two-term kernel)
   wait_vmem();  // no copy into this wave's buffers is still in flight
   pw = wave_sum(pw);
   pv = wave_sum(pv);
@@ -608,6 +609,10 @@ __global__ __launch_bounds__(kThreads, 4) void csr3_stream_kernel(CsrDev t1, Csr
     }
     a.partials[blockIdx.x] = bw;
     if (a.first) a.partials[gridDim.x + blockIdx.x] = bv;
+  }
+  if (my_valid) {
+    a.wout[my_row] = fromd2(res_w);
+    a.pacc[my_row] = fromd2(res_p);
   }
 }
 
