@@ -46,8 +46,19 @@ __global__ __launch_bounds__(T::THREADS) void dense_mfma_leja_kernel(const doubl
                                                                      long long ld, int dim, MultiArgs a) {
   constexpr int TI = T::TI, TJ = T::TJ, KS = T::KS, WM = T::WM, WN = T::WN, TM = T::TM, TN = T::TN;
   constexpr int HU = T::HU, WU = T::WU;
-  __shared__ double sHre[KS][NT][TM][TK + 1], sHim[KS][NT][TM][TK + 1];
-  __shared__ double sWre[KS][TK][TN + 1], sWim[KS][TK][TN + 1];
+  // Row strides chosen so that the operand reads of one MFMA step hit distinct
+  // LDS banks (64 banks of 4 bytes, 32 lanes of 8-byte reads per pass).  W:
+  // lanes l and l + 16 read rows kk and kk + 1, 16 consecutive states each,
+  // so the stride is 16 doubles past a multiple of 32 (with TN + 1 nearly
+  // every lane of the second half met one of the first).  H: the 16 rows of
+  // an operand start a stride apart, and a stride of 2 mod 4 doubles with an
+  // odd half (18 for TK = 16) puts them on sixteen distinct multiples of 4
+  // banks, the next k (lanes 16..31) on the pairs in between.
+  constexpr int kHStride = TK + 2, kWStride = TN + 16;
+  static_assert(kHStride % 4 == 2 && (kHStride / 2) % 2 == 1, "H operand reads free of bank conflicts");
+  static_assert(kWStride % 32 == 16, "W operand reads free of bank conflicts");
+  __shared__ double sHre[KS][NT][TM][kHStride], sHim[KS][NT][TM][kHStride];
+  __shared__ double sWre[KS][TK][kWStride], sWim[KS][TK][kWStride];
   __shared__ double csum[2][2][TN];  // [row half][w|v][state]
   __shared__ int sstop_any;
   const int B = a.B;
