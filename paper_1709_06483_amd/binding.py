@@ -304,7 +304,7 @@ CSR_VARIANTS = {1: "nonzero streaming", 2: "row per lane, 64 rows", 3: "row per 
 
 DENSE_ROWS_PER_WAVE = (1, 2, 4)
 MFMA_TILES = {0: "32x64, K split in two", 1: "32x64", 2: "64x64", 3: "64x64, K split in two",
-              4: "32x128, K split in two"}
+              4: "32x128, K split in two", 5: "32x64, LDS-DMA staging"}
 
 
 def magnus_autotune(ctx: Context, ham: DeviceHamiltonian, batch: int = 1) -> dict:
@@ -315,7 +315,7 @@ def magnus_autotune(ctx: Context, ham: DeviceHamiltonian, batch: int = 1) -> dic
     and the timings."""
     v, g = C.c_int32(), C.c_int32()
     vus = np.zeros(len(CSR_VARIANTS))
-    gus = np.zeros(5)
+    gus = np.zeros(len(MFMA_TILES))
     _check(lib().magnus_autotune(ctx.handle, C.byref(ham.struct), batch, C.byref(v), C.byref(g), _dptr(vus),
                                  _dptr(gus), _stream()))
     if ham.struct.H1.format == DENSE:

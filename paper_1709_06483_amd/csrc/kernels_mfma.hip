@@ -7,7 +7,8 @@
 // NT = 1: one (assembled) matrix, y_b = a1_b (H w_b).
 // NT = 2: two terms with per-state coefficients folded into the W operand,
 //         y_b = H1 (a1_b w_b) + H2 (a2_b w_b).
-// Several tile shapes (kMfmaTiles, chosen per problem by magnus_autotune):
+// Several tile shapes (kMfmaTiles, chosen per problem by magnus_autotune;
+// the LDS-DMA variant further down is the sixth):
 // a wave computes TI x TJ MFMA tiles, four waves per K group a 32 TI x 32 TJ
 // block of rows x states; K is staged through LDS 16 at a time with the next
 // chunk prefetched into registers while the MFMAs run.
@@ -22,6 +23,10 @@ using namespace dev;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int TK = 16;
+
+__device__ __forceinline__ unsigned dma_lds_offset(const void* p) {
+  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
 
 // Tile shape of one instantiation: a wave computes TI x TJ MFMA tiles of
 // 16 x 16 (16 TI rows, 16 TJ states), four waves per K group in a 2 x 2
@@ -40,6 +45,79 @@ struct MfmaTile {
   static constexpr int HU = TM * TK / kThreads;  // H elements per thread and term (consecutive along K)
   static constexpr int WU = TK * TN / kThreads;  // W elements per thread (consecutive states)
 };
+
+// Epilogue of a group iteration, called by every thread: the Leja update of
+// the workgroup's TM x TN block from the accumulators (element j of a lane's
+// v4d is row lane/16 + 4 j of its 16-row tile, state lane % 16, the
+// v_mfma_f64_16x16x4f64 output layout), and the per-state norm partials of
+// the block, stored column-major (state, 32-row block) as the decide kernel
+// reads them (a tile of TM rows writes its sums at its first 32-row block,
+// zeros at the others).  epi: this thread's accumulators hold the sums.
+template <int NT, int TI, int TJ, int WM, int WN, int TM, int TN>
+__device__ __forceinline__ void group_epilogue(const MultiArgs& a, int dim, int row0, int col0, int wr, int wc,
+                                               bool epi, const v4d (&are)[TI][TJ], const v4d (&aim)[TI][TJ],
+                                               double (&csum)[2][2][TN]) {
+  const int B = a.B;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const d2* W = reinterpret_cast<const d2*>(a.x);
+  double pw[TJ], pv[TJ];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    pw[tj] = 0.0;
+    pv[tj] = 0.0;
+    const int c = col0 + wc * WN + tj * 16 + (lane & 15);
+    if (!epi || c >= B) continue;
+    const ColParam P = a.prm[c];
+    const bool stopped_c = a.check_stop ? load_stopped(&a.slots[c]) != 0 : false;
+    const double ys = NT == 2 ? 1.0 : P.a1;
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + wr * WM + ti * 16 + (lane >> 4) + 4 * j;
+        if (r >= dim) continue;
+        const long long idx = (long long)r * B + c;
+        const d2 y = d2{ys * are[ti][tj][j], ys * aim[ti][tj][j]};
+        const d2 w_old = W[idx];
+        const d2 wn = y - rmul(P.sigma, w_old);
+        const d2 dd = {P.dre, P.dim};
+        d2 p;
+        if (a.first) {
+          p = cmul(d2{P.d0re, P.d0im}, w_old) + cmul(dd, wn);
+          pv[tj] += nrm2(w_old);
+        } else {
+          p = tod2(a.pacc[idx]);
+          if (!stopped_c) p += cmul(dd, wn);
+        }
+        a.wout[idx] = fromd2(wn);
+        a.pacc[idx] = fromd2(p);
+        pw[tj] += nrm2(wn);
+      }
+  }
+  // per-state sums: lanes l, l + 16, l + 32, l + 48 share a state
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    pw[tj] += __shfl_xor(pw[tj], 16, 64);
+    pw[tj] += __shfl_xor(pw[tj], 32, 64);
+    pv[tj] += __shfl_xor(pv[tj], 16, 64);
+    pv[tj] += __shfl_xor(pv[tj], 32, 64);
+    if (epi && lane < 16) {
+      csum[wr][0][wc * WN + tj * 16 + lane] = pw[tj];
+      csum[wr][1][wc * WN + tj * 16 + lane] = pv[tj];
+    }
+  }
+  __syncthreads();
+  if (tid < TN && col0 + tid < B) {
+    const int rb32 = row0 / 32, nrb32 = (dim + 31) / 32;
+    const long long o = ((long long)(col0 + tid) * nrb32 + rb32) * 2;
+    a.partials[o] = csum[0][0][tid] + csum[1][0][tid];
+    a.partials[o + 1] = csum[0][1][tid] + csum[1][1][tid];
+    for (int q = 1; q < TM / 32 && rb32 + q < nrb32; ++q) {
+      a.partials[o + 2 * q] = 0.0;
+      a.partials[o + 2 * q + 1] = 0.0;
+    }
+  }
+}
 
 template <int NT, class T>
 __global__ __launch_bounds__(T::THREADS) void dense_mfma_leja_kernel(const double2* H1, const double2* H2,
@@ -243,68 +321,182 @@ __global__ __launch_bounds__(T::THREADS) void dense_mfma_leja_kernel(const doubl
         }
   }
   const bool epi = kg == 0;  // group 0 holds the sums; the others only keep the barrier count
+  group_epilogue<NT, TI, TJ, WM, WN, TM, TN>(a, dim, row0, col0, wr, wc, epi, are, aim, csum);
+}
 
-  // epilogue: accumulator element j of a lane is row lane/16 + 4 j of its
-  // 16-row tile, state lane % 16 (the v_mfma_f64_16x16x4f64 output layout)
-  double pw[TJ], pv[TJ];
-#pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) {
-    pw[tj] = 0.0;
-    pv[tj] = 0.0;
-    const int c = col0 + wc * WN + tj * 16 + (lane & 15);
-    if (!epi || c >= B) continue;
-    const ColParam P = a.prm[c];
-    const bool stopped_c = a.check_stop ? load_stopped(&a.slots[c]) != 0 : false;
-    const double ys = NT == 2 ? 1.0 : P.a1;
-#pragma unroll
-    for (int ti = 0; ti < TI; ++ti)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = row0 + wr * WM + ti * 16 + (lane >> 4) + 4 * j;
-        if (r >= dim) continue;
-        const long long idx = (long long)r * B + c;
-        const d2 y = d2{ys * are[ti][tj][j], ys * aim[ti][tj][j]};
-        const d2 w_old = W[idx];
-        const d2 wn = y - rmul(P.sigma, w_old);
-        const d2 dd = {P.dre, P.dim};
-        d2 p;
-        if (a.first) {
-          p = cmul(d2{P.d0re, P.d0im}, w_old) + cmul(dd, wn);
-          pv[tj] += nrm2(w_old);
-        } else {
-          p = tod2(a.pacc[idx]);
-          if (!stopped_c) p += cmul(dd, wn);
-        }
-        a.wout[idx] = fromd2(wn);
-        a.pacc[idx] = fromd2(p);
-        pw[tj] += nrm2(wn);
-      }
+// ---------------------------------------------------------------------------
+// The same iteration with the operands staged by LDS-DMA: each K chunk of
+// the H block (TM rows x TK) and of the W block (TK x TN states) goes from
+// memory straight into LDS with global_load_lds (no registers held while in
+// flight), three chunks deep, so a workgroup passes one barrier per chunk:
+// at the top of chunk c every wave waits until its own copies of chunk c
+// have landed (only chunk c + 1's remain in flight), the barrier then
+// covers everybody's copies and everybody's reads of chunk c - 1, whose
+// buffer takes chunk c + 2's copies.  The copies place complex elements
+// k-major (slot k * TM + r for H, k * TN + c for W; a copy's lanes may load
+// any addresses, so the transposition of the row-major H is free), which
+// makes each MFMA step's operand reads 16-byte reads of 16 consecutive slots:
+// one read gives a lane both halves of its complex operand, free of bank
+// conflicts.  The copies are issued from inline asm, so the compiler, which
+// does not see them, neither makes every LDS read wait for all copies in
+// flight (it cannot tell the buffers apart) nor holds the operand reads
+// back: it schedules them as ordinary LDS loads ahead of the MFMAs that use
+// them.  The waits for the copies are explicit (before each barrier, and for
+// all of them before the epilogue and before the first copy, so the
+// compiler's own count of outstanding loads stays an upper bound).  The
+// three buffers are separate LDS arrays and the chunk loop is unrolled by
+// three, so every buffer index is a constant.  Tile: 32 rows x 64 states per
+// workgroup of four waves (16 x 32 each).
+constexpr int kDmaTK = 16;
+
+// One 16-byte-per-lane copy from memory into LDS at lds + 16 * lane (lds
+// wave-uniform); M0 takes the LDS address, and the copy reads M0 one wait
+// state after it was written.
+__device__ __forceinline__ void dma16(const void* src, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds) : "memory", "m0");
+}
+
+// The LDS staging buffers of the LDS-DMA tile, one pair of arrays per buffer.
+template <int NT, int BUF>
+struct DmaBuf {
+  static __device__ __forceinline__ d2 (&h())[NT][kDmaTK][32] {
+    __shared__ d2 a[NT][kDmaTK][32];
+    return a;
   }
-  // per-state sums: lanes l, l + 16, l + 32, l + 48 share a state
-#pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) {
-    pw[tj] += __shfl_xor(pw[tj], 16, 64);
-    pw[tj] += __shfl_xor(pw[tj], 32, 64);
-    pv[tj] += __shfl_xor(pv[tj], 16, 64);
-    pv[tj] += __shfl_xor(pv[tj], 32, 64);
-    if (epi && lane < 16) {
-      csum[wr][0][wc * WN + tj * 16 + lane] = pw[tj];
-      csum[wr][1][wc * WN + tj * 16 + lane] = pv[tj];
-    }
+  static __device__ __forceinline__ d2 (&w())[kDmaTK][64] {
+    __shared__ d2 a[kDmaTK][64];
+    return a;
+  }
+};
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void dense_mfma_dma_kernel(const double2* H1, const double2* H2, long long ld,
+                                                                  int dim, MultiArgs a) {
+  constexpr int TI = 1, TJ = 2, WM = 16, WN = 32, TM = 32, TN = 64, TK = kDmaTK;
+  constexpr int kHOps = NT * (TM * TK / 64) / 4;  // copy instructions per wave and chunk: H
+  constexpr int kWOps = (TK * TN / 64) / 4;       // and W
+  constexpr int kOps = kHOps + kWOps;
+  static_assert(kOps < 16, "vmcnt field");
+  __shared__ double csum[2][2][TN];  // [row half][w|v][state]
+  __shared__ int sstop_any;
+  const int B = a.B;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wv >> 1, wc = wv & 1;  // wave position in the 2 x 2 arrangement
+
+  // block coordinates: the column blocks of one row block share an XCD
+  const int gx = (B + TN - 1) / TN;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int rb = L / gx, cb = L % gx;
+  const int row0 = rb * TM, col0 = cb * TN;
+
+  if (tid == 0) {
+    int any_running = 0;
+    for (int c = col0; c < min(B, col0 + TN); ++c)
+      any_running |= a.check_stop ? !load_stopped(&a.slots[c]) : 1;
+    sstop_any = any_running;
   }
   __syncthreads();
-  if (tid < TN && col0 + tid < B) {
-    // column-major (state, 32-row block), as the decide kernel reads them: a
-    // tile of TM rows writes its sums at its first 32-row block, zeros at the others
-    const int rb32 = row0 / 32, nrb32 = (dim + 31) / 32;
-    const long long o = ((long long)(col0 + tid) * nrb32 + rb32) * 2;
-    a.partials[o] = csum[0][0][tid] + csum[1][0][tid];
-    a.partials[o + 1] = csum[0][1][tid] + csum[1][1][tid];
-    for (int q = 1; q < TM / 32 && rb32 + q < nrb32; ++q) {
-      a.partials[o + 2 * q] = 0.0;
-      a.partials[o + 2 * q + 1] = 0.0;
-    }
+  if (!sstop_any) return;  // every state of this block has stopped (uniform)
+
+  // per-lane operand scale factors (NT = 2): columns of this lane's B operands
+  double sc[NT][TJ];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    const int c = col0 + wc * WN + tj * 16 + (lane & 15);
+    const ColParam P = a.prm[c < B ? c : 0];
+    sc[0][tj] = NT == 2 ? P.a1 : 1.0;
+    if constexpr (NT == 2) sc[1][tj] = P.a2;
   }
+
+  const d2* W = reinterpret_cast<const d2*>(a.x);
+  const d2* Hp[2] = {reinterpret_cast<const d2*>(H1), reinterpret_cast<const d2*>(H2)};
+  // copies of K chunk kc (from entry kc * TK) into buffer buf; indices
+  // clamped into the matrix (rows past dim and states past B reach only
+  // outputs that are never stored; entries past dim along K are zeroed on the
+  // W side when they are read), so every wave issues exactly kOps copies per chunk
+  auto copy_chunk = [&](int kc, auto buf) {
+    constexpr int BF = decltype(buf)::value;
+    auto& sh = DmaBuf<NT, BF>::h();
+    auto& sw = DmaBuf<NT, BF>::w();
+    const int k0 = kc * TK;
+#pragma unroll
+    for (int i = 0; i < kHOps; ++i) {
+      const int u = wv * kHOps + i;  // the workgroup's H copy u: term u / 8, slots (u % 8) * 64 + lane
+      const int t = u / (TM * TK / 64), iu = u % (TM * TK / 64);
+      const int sl = iu * 64 + lane;
+      const int k = sl / TM, r = sl % TM;
+      const int row = min(row0 + r, dim - 1), col = min(k0 + k, dim - 1);
+      dma16(Hp[t] + (long long)row * ld + col, dma_lds_offset(&sh[t][iu * 64 / TM][0]));
+    }
+#pragma unroll
+    for (int i = 0; i < kWOps; ++i) {
+      const int k = wv * kWOps + i;  // the workgroup's W copy k: row k of the chunk
+      const int kr = min(k0 + k, dim - 1), c = min(col0 + lane, B - 1);
+      dma16(W + (long long)kr * B + c, dma_lds_offset(&sw[k][0]));
+    }
+  };
+
+  v4d are[TI][TJ], aim[TI][TJ];
+#pragma unroll
+  for (int tj = 0; tj < TJ; ++tj) {
+    are[0][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+    aim[0][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  const int nk = (dim + TK - 1) / TK;
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loads above are done before the first copy
+  copy_chunk(0, std::integral_constant<int, 0>{});
+  copy_chunk(1, std::integral_constant<int, 1>{});
+  // this lane's operands: H row hr, W states wc * WN + tj * 16 + lane % 16, K offset kq
+  const int hr = wr * WM + (lane & 15), kq = lane >> 4;
+  // chunk kc from buffer buf: wait for it, release chunk kc - 1's buffer to
+  // chunk kc + 2's copies (past the end: clamped, unused), multiply
+  auto chunk = [&](int kc, auto buf) {
+    constexpr int BF = decltype(buf)::value;
+    auto& sh = DmaBuf<NT, BF>::h();
+    auto& sw = DmaBuf<NT, BF>::w();
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(kOps) : "memory");
+    copy_chunk(kc + 2, std::integral_constant<int, (BF + 2) % 3>{});
+    const int k0 = kc * TK;
+#pragma unroll
+    for (int ks = 0; ks < TK / 4; ++ks) {
+      const bool k_in = k0 + ks * 4 + kq < dim;
+      d2 h[NT], wv2[TJ];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) h[t] = sh[t][ks * 4 + kq][hr];
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj) {
+        wv2[tj] = sw[ks * 4 + kq][wc * WN + tj * 16 + (lane & 15)];
+        if (!k_in) wv2[tj] = d2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        double wre[TJ], wim[TJ];
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+          wre[tj] = wv2[tj].x * sc[t][tj];
+          wim[tj] = wv2[tj].y * sc[t][tj];
+        }
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+          are[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].x, wre[tj], are[0][tj], 0, 0, 0);
+          aim[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].x, wim[tj], aim[0][tj], 0, 0, 0);
+        }
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+          are[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-h[t].y, wim[tj], are[0][tj], 0, 0, 0);
+          aim[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].y, wre[tj], aim[0][tj], 0, 0, 0);
+        }
+      }
+    }
+  };
+  for (int kc = 0; kc < nk; kc += 3) {
+    chunk(kc, std::integral_constant<int, 0>{});
+    if (kc + 1 < nk) chunk(kc + 1, std::integral_constant<int, 1>{});
+    if (kc + 2 < nk) chunk(kc + 2, std::integral_constant<int, 2>{});
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): no copy into this workgroup's LDS is still in flight
+  group_epilogue<NT, TI, TJ, WM, WN, TM, TN>(a, dim, row0, col0, wr, wc, true, are, aim, csum);
 }
 
 // H = a H1 + b H2 (+ k K) (row-major, row stride ld for H1, H2, dim for K and out).
@@ -350,6 +542,13 @@ hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, l
     case 2: return launch_mfma_tile<MfmaTile<2, 2, 1>>(nterms, H1, H2, ld, dim, a, s);  // 64 x 64
     case 3: return launch_mfma_tile<MfmaTile<2, 2, 2>>(nterms, H1, H2, ld, dim, a, s);  // 64 x 64, K split in two
     case 4: return launch_mfma_tile<MfmaTile<1, 4, 2>>(nterms, H1, H2, ld, dim, a, s);  // 32 x 128, K split in two
+    case 5: {  // 32 x 64, operands staged by LDS-DMA three chunks deep
+      const int gx = (a.B + 63) / 64;
+      const int grid = (dim + 31) / 32 * gx;
+      if (nterms == 1) dense_mfma_dma_kernel<1><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
+      else dense_mfma_dma_kernel<2><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
+      return hipGetLastError();
+    }
     default: return hipErrorInvalidValue;
   }
 }

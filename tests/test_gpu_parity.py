@@ -414,14 +414,18 @@ def test_dense_batched_mfma_matches_oracle(reserve, per_state, N):
     c.close()
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("tile,N,Bn", [(0, 300, 70), (1, 300, 70), (2, 300, 70), (3, 300, 70), (4, 300, 70),
+                                        (5, 300, 70), (5, 5, 2), (5, 33, 65), (5, 48, 64)])
 @pytest.mark.parametrize("reserve", [True, False])
-def test_dense_mfma_tile_shapes_match_oracle(tile, reserve, monkeypatch):
+def test_dense_mfma_tile_shapes_match_oracle(tile, N, Bn, reserve, monkeypatch):
     """Every FP64-MFMA tile shape the autotuner chooses from (32 x 64 and 64 x 64
-    rows x states with and without the K split, 32 x 128 with it) on a ragged
-    dim and batch, one term (assembled) and two."""
+    rows x states with and without the K split, 32 x 128 with it, 32 x 64 staged
+    by LDS-DMA) on a ragged dim and batch, one term (assembled) and two; the
+    LDS-DMA tile also on one partial K chunk (N = 5), a chunk and a ragged tail
+    (N = 33, one state past a column block) and whole chunks and blocks (N = 48,
+    64 states)."""
     monkeypatch.setenv("MAGNUS_MFMA_TILE", str(tile))
-    N, Bn, tau, nsteps = 300, 70, 0.005, 4
+    tau, nsteps = 0.005, 4
     H0 = inputs.powerlaw_hermitian(N, 1.5, seed=31)
     V = inputs.powerlaw_hermitian(N, 1.5, seed=32)
     c = B.Context(max_dim=N, max_batch=Bn)
@@ -437,7 +441,7 @@ def test_dense_mfma_tile_shapes_match_oracle(tile, reserve, monkeypatch):
     assert c.timing_read(B.KERNEL_DENSE_MFMA)[1] > 0
     c.timing(False)
     out = host(psi)
-    for k in (0, 37, Bn - 1):
+    for k in sorted({0, min(37, Bn - 1), Bn - 1}):
         ref = mg.propagate("CF4", mg.two_term(H0, V, f), tau, nsteps, psi0[k], expm="eig")
         assert rel(out[k], ref) <= BUDGET, k
     c.close()
