@@ -424,7 +424,7 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
  * rounding (another summation order); the MAGNUS_CSR_VARIANT environment
  * variable, when set, still wins.  Overwrites the context's work vectors.
  *   variant, group       HOST out (may be NULL): the chosen code and group size
- *   variant_us[7], group_us[6]  HOST out (may be NULL): measured microseconds per
+ *   variant_us[7], group_us[7]  HOST out (may be NULL): measured microseconds per
  *                        iteration (a mapping whose grid is too large for the
  *                        stop test fused into the iteration is timed with the
  *                        decide kernel that then follows each iteration; group
@@ -433,11 +433,11 @@ int magnus_propagate_adjoint(magnus_ctx* ctx, const magnus_hamiltonian* h, doubl
  * wave and, when batch > 1, the FP64-MFMA group iteration of batch states
  * with each tile shape (0: 32 rows x 64 states with K split between two
  * groups of four waves, 1: 32 x 64, 2: 64 x 64, 3: 64 x 64 with K split,
- * 4: 32 x 128 with K split, 5: 32 x 64 with the operands copied into LDS by
- * LDS-DMA three chunks deep; one term when the context holds an assembly
+ * 4: 32 x 128 with K split, 5: 32 x 64 and 6: 64 x 64 with the operands
+ * copied into LDS by LDS-DMA three chunks deep; one term when the context holds an assembly
  * buffer, else two), and keeps the fastest for these terms (H1's values and
  * dim); then variant receives the rows per wave, group the tile code,
- * variant_us[0..2] and group_us[0..5] the timings (CSR terms: group_us[0..4]).
+ * variant_us[0..2] and group_us[0..6] the timings (CSR terms: group_us[0..4]).
  * Synchronous.  Errors: EINVAL, ENOMEM, EHIP. */
 int magnus_autotune(magnus_ctx* ctx, const magnus_hamiltonian* h, int32_t batch, int32_t* variant,
                     int32_t* group, double* variant_us, double* group_us, magnus_stream stream);

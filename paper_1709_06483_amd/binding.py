@@ -304,7 +304,8 @@ CSR_VARIANTS = {1: "nonzero streaming", 2: "row per lane, 64 rows", 3: "row per 
 
 DENSE_ROWS_PER_WAVE = (1, 2, 4)
 MFMA_TILES = {0: "32x64, K split in two", 1: "32x64", 2: "64x64", 3: "64x64, K split in two",
-              4: "32x128, K split in two", 5: "32x64, LDS-DMA staging"}
+              4: "32x128, K split in two", 5: "32x64, LDS-DMA staging",
+              6: "64x64, LDS-DMA staging"}
 
 
 def magnus_autotune(ctx: Context, ham: DeviceHamiltonian, batch: int = 1) -> dict:

@@ -143,7 +143,7 @@ struct magnus_ctx {
   // wave of the GEMV iteration and the FP64-MFMA tile of group iterations
   std::map<std::pair<const void*, int64_t>, int> tuned_dense_rpw, tuned_mfma;
   int dense_rpw_env = 0;   // MAGNUS_DENSE_RPW: 1, 2 or 4 rows per wave of the GEMV iteration (0: tuned or 2)
-  int mfma_tile_env = -1;  // MAGNUS_MFMA_TILE: 0..5 forces an FP64-MFMA tile shape (-1: tuned or 0)
+  int mfma_tile_env = -1;  // MAGNUS_MFMA_TILE: 0..6 forces an FP64-MFMA tile shape (-1: tuned or 0)
   int timing = 0;  // 0 off, k >= 1: every k-th launch of each kernel class is bracketed
   int64_t timing_seq[MAGNUS_KERNEL_CSR_LEJA3 + 1] = {};  // launches of each class since enabling
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;

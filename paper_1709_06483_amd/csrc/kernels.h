@@ -251,7 +251,7 @@ hipError_t launch_unpack(const double2* src, double2* dst, int dim, int B, hipSt
 // Partials are written per 32-row block: decide with dense_mfma_row_blocks(dim).
 // tile: 0 32 x 64 with K split in two (default), 1 32 x 64, 2 64 x 64,
 // 3 64 x 64 with K split in two, 4 32 x 128 with K split in two (rows x states).
-constexpr int kMfmaTiles = 6;
+constexpr int kMfmaTiles = 7;
 hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
                              const MultiArgs& a, hipStream_t s, int tile = 0);
 int dense_mfma_row_blocks(int dim);

@@ -8,7 +8,7 @@
 // NT = 2: two terms with per-state coefficients folded into the W operand,
 //         y_b = H1 (a1_b w_b) + H2 (a2_b w_b).
 // Several tile shapes (kMfmaTiles, chosen per problem by magnus_autotune;
-// the LDS-DMA variant further down is the sixth):
+// the LDS-DMA variants further down are the sixth and seventh):
 // a wave computes TI x TJ MFMA tiles, four waves per K group a 32 TI x 32 TJ
 // block of rows x states; K is staged through LDS 16 at a time with the next
 // chunk prefetched into registers while the MFMAs run.
@@ -56,7 +56,7 @@ struct MfmaTile {
 template <int NT, int TI, int TJ, int WM, int WN, int TM, int TN>
 __device__ __forceinline__ void group_epilogue(const MultiArgs& a, int dim, int row0, int col0, int wr, int wc,
                                                bool epi, const v4d (&are)[TI][TJ], const v4d (&aim)[TI][TJ],
-                                               double (&csum)[2][2][TN]) {
+                                               double (&csum)[TM / WM][2][TN]) {
   const int B = a.B;
   const int tid = threadIdx.x, lane = tid & 63;
   const d2* W = reinterpret_cast<const d2*>(a.x);
@@ -110,11 +110,19 @@ __device__ __forceinline__ void group_epilogue(const MultiArgs& a, int dim, int 
   if (tid < TN && col0 + tid < B) {
     const int rb32 = row0 / 32, nrb32 = (dim + 31) / 32;
     const long long o = ((long long)(col0 + tid) * nrb32 + rb32) * 2;
-    a.partials[o] = csum[0][0][tid] + csum[1][0][tid];
-    a.partials[o + 1] = csum[0][1][tid] + csum[1][1][tid];
-    for (int q = 1; q < TM / 32 && rb32 + q < nrb32; ++q) {
-      a.partials[o + 2 * q] = 0.0;
-      a.partials[o + 2 * q + 1] = 0.0;
+    if constexpr (TM / WM == 2) {  // two rows of waves: the tile's sums in its first 32-row block
+      a.partials[o] = csum[0][0][tid] + csum[1][0][tid];
+      a.partials[o + 1] = csum[0][1][tid] + csum[1][1][tid];
+      for (int q = 1; q < TM / 32 && rb32 + q < nrb32; ++q) {
+        a.partials[o + 2 * q] = 0.0;
+        a.partials[o + 2 * q + 1] = 0.0;
+      }
+    } else {  // rows of 16-row waves: two of them per 32-row block
+      static_assert(WM == 16, "two rows of waves per 32-row block");
+      for (int q = 0; q < TM / 32 && rb32 + q < nrb32; ++q) {
+        a.partials[o + 2 * q] = csum[2 * q][0][tid] + csum[2 * q + 1][0][tid];
+        a.partials[o + 2 * q + 1] = csum[2 * q][1][tid] + csum[2 * q + 1][1][tid];
+      }
     }
   }
 }
@@ -345,8 +353,7 @@ __global__ __launch_bounds__(T::THREADS) void dense_mfma_leja_kernel(const doubl
 // all of them before the epilogue and before the first copy, so the
 // compiler's own count of outstanding loads stays an upper bound).  The
 // three buffers are separate LDS arrays and the chunk loop is unrolled by
-// three, so every buffer index is a constant.  Tile: 32 rows x 64 states per
-// workgroup of four waves (16 x 32 each).
+// three, so every buffer index is a constant.
 constexpr int kDmaTK = 16;
 
 // One 16-byte-per-lane copy from memory into LDS at lds + 16 * lane (lds
@@ -356,11 +363,11 @@ __device__ __forceinline__ void dma16(const void* src, unsigned lds) {
   asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds) : "memory", "m0");
 }
 
-// The LDS staging buffers of the LDS-DMA tile, one pair of arrays per buffer.
-template <int NT, int BUF>
+// The LDS staging buffers of the LDS-DMA tiles, one pair of arrays per buffer.
+template <int NT, int TM, int BUF>
 struct DmaBuf {
-  static __device__ __forceinline__ d2 (&h())[NT][kDmaTK][32] {
-    __shared__ d2 a[NT][kDmaTK][32];
+  static __device__ __forceinline__ d2 (&h())[NT][kDmaTK][TM] {
+    __shared__ d2 a[NT][kDmaTK][TM];
     return a;
   }
   static __device__ __forceinline__ d2 (&w())[kDmaTK][64] {
@@ -369,20 +376,27 @@ struct DmaBuf {
   }
 };
 
-template <int NT>
-__global__ __launch_bounds__(kThreads) void dense_mfma_dma_kernel(const double2* H1, const double2* H2, long long ld,
-                                                                  int dim, MultiArgs a) {
-  constexpr int TI = 1, TJ = 2, WM = 16, WN = 32, TM = 32, TN = 64, TK = kDmaTK;
-  constexpr int kHOps = NT * (TM * TK / 64) / 4;  // copy instructions per wave and chunk: H
-  constexpr int kWOps = (TK * TN / 64) / 4;       // and W
+// TM rows (32 or 64) x 64 states per workgroup of TM / 8 waves, each wave
+// 16 rows x 32 states.  TAIL: dim is not a multiple of the chunk, so the W
+// operand entries past dim are zeroed as they are read and the last chunk's
+// copies clamp their indices.
+template <int NT, int TM, bool TAIL>
+__global__ __launch_bounds__(TM * 8) void dense_mfma_dma_kernel(const double2* H1, const double2* H2, long long ld,
+                                                                int dim, MultiArgs a) {
+  constexpr int TI = 1, TJ = 2, WM = 16, WN = 32, TN = 64, TK = kDmaTK;
+  constexpr int NW = TM / 8;                      // waves
+  constexpr int kHCopies = TM * TK / 64;          // copies of one term's H chunk per workgroup
+  constexpr int kHOps = NT * kHCopies / NW;       // copy instructions per wave and chunk: H
+  constexpr int kWOps = TK * TN / 64 / NW;        // and W
   constexpr int kOps = kHOps + kWOps;
   static_assert(kOps < 16, "vmcnt field");
-  __shared__ double csum[2][2][TN];  // [row half][w|v][state]
+  static_assert(kHCopies % NW == 0 && (TK * TN / 64) % NW == 0, "copies spread evenly over the waves");
+  __shared__ double csum[TM / WM][2][TN];  // [row of waves][w|v][state]
   __shared__ int sstop_any;
   const int B = a.B;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wv >> 1, wc = wv & 1;  // wave position in the 2 x 2 arrangement
+  const int wr = wv >> 1, wc = wv & 1;  // wave position: TM / 16 rows x 2 columns of waves
 
   // block coordinates: the column blocks of one row block share an XCD
   const int gx = (B + TN - 1) / TN;
@@ -411,29 +425,39 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_dma_kernel(const double2*
 
   const d2* W = reinterpret_cast<const d2*>(a.x);
   const d2* Hp[2] = {reinterpret_cast<const d2*>(H1), reinterpret_cast<const d2*>(H2)};
-  // copies of K chunk kc (from entry kc * TK) into buffer buf; indices
-  // clamped into the matrix (rows past dim and states past B reach only
-  // outputs that are never stored; entries past dim along K are zeroed on the
-  // W side when they are read), so every wave issues exactly kOps copies per chunk
+  // This wave's copies: H copy u of the workgroup covers term u / kHCopies,
+  // slots (u % kHCopies) * 64 + lane = k * TM + r, at LDS offset hdst; W copy
+  // k covers row k of the chunk.
+  unsigned hdst[kHOps];
+#pragma unroll
+  for (int i = 0; i < kHOps; ++i) {
+    const int u = wv * kHOps + i;
+    hdst[i] = (unsigned)(((u / kHCopies) * TK * TM + (u % kHCopies) * 64) * sizeof(d2));
+  }
+  const int wcol = min(col0 + lane, B - 1);
+  const int nk = (dim + TK - 1) / TK;
+  // copies of K chunk kc into buffer buf, without a branch: past the last
+  // chunk they copy the last one again (unused); indices clamped into the
+  // matrix (rows past dim and states past B reach only outputs that are never
+  // stored; entries past dim along K, with TAIL, are zeroed on the W side
+  // when read)
   auto copy_chunk = [&](int kc, auto buf) {
     constexpr int BF = decltype(buf)::value;
-    auto& sh = DmaBuf<NT, BF>::h();
-    auto& sw = DmaBuf<NT, BF>::w();
-    const int k0 = kc * TK;
+    const unsigned hb = dma_lds_offset(&DmaBuf<NT, TM, BF>::h()[0][0][0]);
+    const unsigned wb = dma_lds_offset(&DmaBuf<NT, TM, BF>::w()[0][0]);
+    const int k0 = min(kc, nk - 1) * TK;
 #pragma unroll
     for (int i = 0; i < kHOps; ++i) {
-      const int u = wv * kHOps + i;  // the workgroup's H copy u: term u / 8, slots (u % 8) * 64 + lane
-      const int t = u / (TM * TK / 64), iu = u % (TM * TK / 64);
-      const int sl = iu * 64 + lane;
-      const int k = sl / TM, r = sl % TM;
-      const int row = min(row0 + r, dim - 1), col = min(k0 + k, dim - 1);
-      dma16(Hp[t] + (long long)row * ld + col, dma_lds_offset(&sh[t][iu * 64 / TM][0]));
+      const int u = wv * kHOps + i;
+      const int t = u / kHCopies, sl = (u % kHCopies) * 64 + lane;
+      const int row = min(row0 + sl % TM, dim - 1), col = min(k0 + sl / TM, dim - 1);
+      dma16(Hp[t] + (long long)row * ld + col, hb + hdst[i]);
     }
 #pragma unroll
     for (int i = 0; i < kWOps; ++i) {
-      const int k = wv * kWOps + i;  // the workgroup's W copy k: row k of the chunk
-      const int kr = min(k0 + k, dim - 1), c = min(col0 + lane, B - 1);
-      dma16(W + (long long)kr * B + c, dma_lds_offset(&sw[k][0]));
+      const int k = wv * kWOps + i;
+      const int kr = min(k0 + k, dim - 1);
+      dma16(W + (long long)kr * B + wcol, wb + (unsigned)(k * TN * sizeof(d2)));
     }
   };
 
@@ -443,24 +467,25 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_dma_kernel(const double2*
     are[0][tj] = v4d{0.0, 0.0, 0.0, 0.0};
     aim[0][tj] = v4d{0.0, 0.0, 0.0, 0.0};
   }
-  const int nk = (dim + TK - 1) / TK;
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loads above are done before the first copy
   copy_chunk(0, std::integral_constant<int, 0>{});
   copy_chunk(1, std::integral_constant<int, 1>{});
   // this lane's operands: H row hr, W states wc * WN + tj * 16 + lane % 16, K offset kq
   const int hr = wr * WM + (lane & 15), kq = lane >> 4;
-  // chunk kc from buffer buf: wait for it, release chunk kc - 1's buffer to
-  // chunk kc + 2's copies (past the end: clamped, unused), multiply
+  // chunk kc from buffer buf: wait for it (with chunk kc + 1's copies still
+  // in flight), release chunk kc - 1's buffer to chunk kc + 2's copies
+  // (issued after the first step's operand reads, which then wait on nothing
+  // but LDS), multiply.  No branch inside, so the compiler may move operand
+  // reads ahead across the steps.
   auto chunk = [&](int kc, auto buf) {
     constexpr int BF = decltype(buf)::value;
-    auto& sh = DmaBuf<NT, BF>::h();
-    auto& sw = DmaBuf<NT, BF>::w();
+    auto& sh = DmaBuf<NT, TM, BF>::h();
+    auto& sw = DmaBuf<NT, TM, BF>::w();
     asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(kOps) : "memory");
-    copy_chunk(kc + 2, std::integral_constant<int, (BF + 2) % 3>{});
     const int k0 = kc * TK;
 #pragma unroll
     for (int ks = 0; ks < TK / 4; ++ks) {
-      const bool k_in = k0 + ks * 4 + kq < dim;
+      const bool k_in = !TAIL || k0 + ks * 4 + kq < dim;
       d2 h[NT], wv2[TJ];
 #pragma unroll
       for (int t = 0; t < NT; ++t) h[t] = sh[t][ks * 4 + kq][hr];
@@ -469,6 +494,7 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_dma_kernel(const double2*
         wv2[tj] = sw[ks * 4 + kq][wc * WN + tj * 16 + (lane & 15)];
         if (!k_in) wv2[tj] = d2{0.0, 0.0};
       }
+      if (ks == 0) copy_chunk(kc + 2, std::integral_constant<int, (BF + 2) % 3>{});
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         double wre[TJ], wim[TJ];
@@ -484,7 +510,8 @@ __global__ __launch_bounds__(kThreads) void dense_mfma_dma_kernel(const double2*
         }
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj) {
-          are[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-h[t].y, wim[tj], are[0][tj], 0, 0, 0);
+          // the last argument sets the MFMA's negate modifier on A: -Him Wim
+          are[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].y, wim[tj], are[0][tj], 0, 0, 1);
           aim[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].y, wre[tj], aim[0][tj], 0, 0, 0);
         }
       }
@@ -532,6 +559,18 @@ hipError_t launch_mfma_tile(int nterms, const double2* H1, const double2* H2, lo
   else dense_mfma_leja_kernel<2, T><<<grid, T::THREADS, 0, s>>>(H1, H2, ld, dim, a);
   return hipGetLastError();
 }
+
+template <int TM>
+hipError_t launch_dma_tile(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
+                           const MultiArgs& a, hipStream_t s) {
+  const int grid = (dim + TM - 1) / TM * ((a.B + 63) / 64);
+  const bool tail = dim % kDmaTK != 0;
+  if (nterms == 1 && tail) dense_mfma_dma_kernel<1, TM, true><<<grid, TM * 8, 0, s>>>(H1, H2, ld, dim, a);
+  else if (nterms == 1) dense_mfma_dma_kernel<1, TM, false><<<grid, TM * 8, 0, s>>>(H1, H2, ld, dim, a);
+  else if (tail) dense_mfma_dma_kernel<2, TM, true><<<grid, TM * 8, 0, s>>>(H1, H2, ld, dim, a);
+  else dense_mfma_dma_kernel<2, TM, false><<<grid, TM * 8, 0, s>>>(H1, H2, ld, dim, a);
+  return hipGetLastError();
+}
 }  // namespace
 
 hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
@@ -542,13 +581,8 @@ hipError_t launch_dense_mfma(int nterms, const double2* H1, const double2* H2, l
     case 2: return launch_mfma_tile<MfmaTile<2, 2, 1>>(nterms, H1, H2, ld, dim, a, s);  // 64 x 64
     case 3: return launch_mfma_tile<MfmaTile<2, 2, 2>>(nterms, H1, H2, ld, dim, a, s);  // 64 x 64, K split in two
     case 4: return launch_mfma_tile<MfmaTile<1, 4, 2>>(nterms, H1, H2, ld, dim, a, s);  // 32 x 128, K split in two
-    case 5: {  // 32 x 64, operands staged by LDS-DMA three chunks deep
-      const int gx = (a.B + 63) / 64;
-      const int grid = (dim + 31) / 32 * gx;
-      if (nterms == 1) dense_mfma_dma_kernel<1><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
-      else dense_mfma_dma_kernel<2><<<grid, kThreads, 0, s>>>(H1, H2, ld, dim, a);
-      return hipGetLastError();
-    }
+    case 5: return launch_dma_tile<32>(nterms, H1, H2, ld, dim, a, s);  // 32 x 64, LDS-DMA staging
+    case 6: return launch_dma_tile<64>(nterms, H1, H2, ld, dim, a, s);  // 64 x 64, LDS-DMA staging
     default: return hipErrorInvalidValue;
   }
 }

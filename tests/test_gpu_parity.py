@@ -415,15 +415,16 @@ def test_dense_batched_mfma_matches_oracle(reserve, per_state, N):
 
 
 @pytest.mark.parametrize("tile,N,Bn", [(0, 300, 70), (1, 300, 70), (2, 300, 70), (3, 300, 70), (4, 300, 70),
-                                        (5, 300, 70), (5, 5, 2), (5, 33, 65), (5, 48, 64)])
+                                        (5, 300, 70), (5, 5, 2), (5, 33, 65), (5, 48, 64),
+                                        (6, 300, 70), (6, 5, 2), (6, 33, 65), (6, 128, 64)])
 @pytest.mark.parametrize("reserve", [True, False])
 def test_dense_mfma_tile_shapes_match_oracle(tile, N, Bn, reserve, monkeypatch):
     """Every FP64-MFMA tile shape the autotuner chooses from (32 x 64 and 64 x 64
-    rows x states with and without the K split, 32 x 128 with it, 32 x 64 staged
-    by LDS-DMA) on a ragged dim and batch, one term (assembled) and two; the
-    LDS-DMA tile also on one partial K chunk (N = 5), a chunk and a ragged tail
-    (N = 33, one state past a column block) and whole chunks and blocks (N = 48,
-    64 states)."""
+    rows x states with and without the K split, 32 x 128 with it, 32 x 64 and
+    64 x 64 staged by LDS-DMA) on a ragged dim and batch, one term (assembled)
+    and two; the LDS-DMA tiles also on one partial K chunk (N = 5), two chunks
+    and a ragged tail (N = 33, one state past a column block) and whole chunks
+    and blocks (N = 48 or 128, 64 states)."""
     monkeypatch.setenv("MAGNUS_MFMA_TILE", str(tile))
     tau, nsteps = 0.005, 4
     H0 = inputs.powerlaw_hermitian(N, 1.5, seed=31)
