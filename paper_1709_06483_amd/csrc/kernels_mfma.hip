@@ -15,18 +15,15 @@
 #include <type_traits>
 
 #include "device_common.h"
+#include "mfma_dma.h"
 
 namespace magnus {
 namespace {
 
 using namespace dev;
-typedef double v4d __attribute__((ext_vector_type(4)));
+using dma_gemm::v4d;
 
 constexpr int TK = 16;
-
-__device__ __forceinline__ unsigned dma_lds_offset(const void* p) {
-  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
-}
 
 // Tile shape of one instantiation: a wave computes TI x TJ MFMA tiles of
 // 16 x 16 (16 TI rows, 16 TJ states), four waves per K group in a 2 x 2
@@ -333,64 +330,13 @@ __global__ __launch_bounds__(T::THREADS) void dense_mfma_leja_kernel(const doubl
 }
 
 // ---------------------------------------------------------------------------
-// The same iteration with the operands staged by LDS-DMA: each K chunk of
-// the H block (TM rows x TK) and of the W block (TK x TN states) goes from
-// memory straight into LDS with global_load_lds (no registers held while in
-// flight), three chunks deep, so a workgroup passes one barrier per chunk:
-// at the top of chunk c every wave waits until its own copies of chunk c
-// have landed (only chunk c + 1's remain in flight), the barrier then
-// covers everybody's copies and everybody's reads of chunk c - 1, whose
-// buffer takes chunk c + 2's copies.  The copies place complex elements
-// k-major (slot k * TM + r for H, k * TN + c for W; a copy's lanes may load
-// any addresses, so the transposition of the row-major H is free), which
-// makes each MFMA step's operand reads 16-byte reads of 16 consecutive slots:
-// one read gives a lane both halves of its complex operand, free of bank
-// conflicts.  The copies are issued from inline asm, so the compiler, which
-// does not see them, neither makes every LDS read wait for all copies in
-// flight (it cannot tell the buffers apart) nor holds the operand reads
-// back: it schedules them as ordinary LDS loads ahead of the MFMAs that use
-// them.  The waits for the copies are explicit (before each barrier, and for
-// all of them before the epilogue and before the first copy, so the
-// compiler's own count of outstanding loads stays an upper bound).  The
-// three buffers are separate LDS arrays and the chunk loop is unrolled by
-// three, so every buffer index is a constant.
-constexpr int kDmaTK = 16;
-
-// One 16-byte-per-lane copy from memory into LDS at lds + 16 * lane (lds
-// wave-uniform); M0 takes the LDS address, and the copy reads M0 one wait
-// state after it was written.
-__device__ __forceinline__ void dma16(const void* src, unsigned lds) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds) : "memory", "m0");
-}
-
-// The LDS staging buffers of the LDS-DMA tiles, one pair of arrays per buffer.
-template <int NT, int TM, int BUF>
-struct DmaBuf {
-  static __device__ __forceinline__ d2 (&h())[NT][kDmaTK][TM] {
-    __shared__ d2 a[NT][kDmaTK][TM];
-    return a;
-  }
-  static __device__ __forceinline__ d2 (&w())[kDmaTK][64] {
-    __shared__ d2 a[kDmaTK][64];
-    return a;
-  }
-};
-
-// TM rows (32 or 64) x 64 states per workgroup of TM / 8 waves, each wave
-// 16 rows x 32 states.  TAIL: dim is not a multiple of the chunk, so the W
-// operand entries past dim are zeroed as they are read and the last chunk's
-// copies clamp their indices.
+// The same iteration on the LDS-DMA tile product (mfma_dma.h): TM rows (32 or
+// 64) x 64 states per workgroup of TM / 8 waves, each wave 16 rows x 32
+// states.  TAIL: dim is not a multiple of the K chunk.
 template <int NT, int TM, bool TAIL>
 __global__ __launch_bounds__(TM * 8) void dense_mfma_dma_kernel(const double2* H1, const double2* H2, long long ld,
                                                                 int dim, MultiArgs a) {
-  constexpr int TI = 1, TJ = 2, WM = 16, WN = 32, TN = 64, TK = kDmaTK;
-  constexpr int NW = TM / 8;                      // waves
-  constexpr int kHCopies = TM * TK / 64;          // copies of one term's H chunk per workgroup
-  constexpr int kHOps = NT * kHCopies / NW;       // copy instructions per wave and chunk: H
-  constexpr int kWOps = TK * TN / 64 / NW;        // and W
-  constexpr int kOps = kHOps + kWOps;
-  static_assert(kOps < 16, "vmcnt field");
-  static_assert(kHCopies % NW == 0 && (TK * TN / 64) % NW == 0, "copies spread evenly over the waves");
+  constexpr int TI = 1, TJ = 2, WM = 16, WN = 32, TN = dma_gemm::kTN;
   __shared__ double csum[TM / WM][2][TN];  // [row of waves][w|v][state]
   __shared__ int sstop_any;
   const int B = a.B;
@@ -422,107 +368,9 @@ __global__ __launch_bounds__(TM * 8) void dense_mfma_dma_kernel(const double2* H
     sc[0][tj] = NT == 2 ? P.a1 : 1.0;
     if constexpr (NT == 2) sc[1][tj] = P.a2;
   }
-
-  const d2* W = reinterpret_cast<const d2*>(a.x);
-  const d2* Hp[2] = {reinterpret_cast<const d2*>(H1), reinterpret_cast<const d2*>(H2)};
-  // This wave's copies: H copy u of the workgroup covers term u / kHCopies,
-  // slots (u % kHCopies) * 64 + lane = k * TM + r, at LDS offset hdst; W copy
-  // k covers row k of the chunk.
-  unsigned hdst[kHOps];
-#pragma unroll
-  for (int i = 0; i < kHOps; ++i) {
-    const int u = wv * kHOps + i;
-    hdst[i] = (unsigned)(((u / kHCopies) * TK * TM + (u % kHCopies) * 64) * sizeof(d2));
-  }
-  const int wcol = min(col0 + lane, B - 1);
-  const int nk = (dim + TK - 1) / TK;
-  // copies of K chunk kc into buffer buf, without a branch: past the last
-  // chunk they copy the last one again (unused); indices clamped into the
-  // matrix (rows past dim and states past B reach only outputs that are never
-  // stored; entries past dim along K, with TAIL, are zeroed on the W side
-  // when read)
-  auto copy_chunk = [&](int kc, auto buf) {
-    constexpr int BF = decltype(buf)::value;
-    const unsigned hb = dma_lds_offset(&DmaBuf<NT, TM, BF>::h()[0][0][0]);
-    const unsigned wb = dma_lds_offset(&DmaBuf<NT, TM, BF>::w()[0][0]);
-    const int k0 = min(kc, nk - 1) * TK;
-#pragma unroll
-    for (int i = 0; i < kHOps; ++i) {
-      const int u = wv * kHOps + i;
-      const int t = u / kHCopies, sl = (u % kHCopies) * 64 + lane;
-      const int row = min(row0 + sl % TM, dim - 1), col = min(k0 + sl / TM, dim - 1);
-      dma16(Hp[t] + (long long)row * ld + col, hb + hdst[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < kWOps; ++i) {
-      const int k = wv * kWOps + i;
-      const int kr = min(k0 + k, dim - 1);
-      dma16(W + (long long)kr * B + wcol, wb + (unsigned)(k * TN * sizeof(d2)));
-    }
-  };
-
   v4d are[TI][TJ], aim[TI][TJ];
-#pragma unroll
-  for (int tj = 0; tj < TJ; ++tj) {
-    are[0][tj] = v4d{0.0, 0.0, 0.0, 0.0};
-    aim[0][tj] = v4d{0.0, 0.0, 0.0, 0.0};
-  }
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loads above are done before the first copy
-  copy_chunk(0, std::integral_constant<int, 0>{});
-  copy_chunk(1, std::integral_constant<int, 1>{});
-  // this lane's operands: H row hr, W states wc * WN + tj * 16 + lane % 16, K offset kq
-  const int hr = wr * WM + (lane & 15), kq = lane >> 4;
-  // chunk kc from buffer buf: wait for it (with chunk kc + 1's copies still
-  // in flight), release chunk kc - 1's buffer to chunk kc + 2's copies
-  // (issued after the first step's operand reads, which then wait on nothing
-  // but LDS), multiply.  No branch inside, so the compiler may move operand
-  // reads ahead across the steps.
-  auto chunk = [&](int kc, auto buf) {
-    constexpr int BF = decltype(buf)::value;
-    auto& sh = DmaBuf<NT, TM, BF>::h();
-    auto& sw = DmaBuf<NT, TM, BF>::w();
-    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(kOps) : "memory");
-    const int k0 = kc * TK;
-#pragma unroll
-    for (int ks = 0; ks < TK / 4; ++ks) {
-      const bool k_in = !TAIL || k0 + ks * 4 + kq < dim;
-      d2 h[NT], wv2[TJ];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) h[t] = sh[t][ks * 4 + kq][hr];
-#pragma unroll
-      for (int tj = 0; tj < TJ; ++tj) {
-        wv2[tj] = sw[ks * 4 + kq][wc * WN + tj * 16 + (lane & 15)];
-        if (!k_in) wv2[tj] = d2{0.0, 0.0};
-      }
-      if (ks == 0) copy_chunk(kc + 2, std::integral_constant<int, (BF + 2) % 3>{});
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        double wre[TJ], wim[TJ];
-#pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) {
-          wre[tj] = wv2[tj].x * sc[t][tj];
-          wim[tj] = wv2[tj].y * sc[t][tj];
-        }
-#pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) {
-          are[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].x, wre[tj], are[0][tj], 0, 0, 0);
-          aim[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].x, wim[tj], aim[0][tj], 0, 0, 0);
-        }
-#pragma unroll
-        for (int tj = 0; tj < TJ; ++tj) {
-          // the last argument sets the MFMA's negate modifier on A: -Him Wim
-          are[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].y, wim[tj], are[0][tj], 0, 0, 1);
-          aim[0][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[t].y, wre[tj], aim[0][tj], 0, 0, 0);
-        }
-      }
-    }
-  };
-  for (int kc = 0; kc < nk; kc += 3) {
-    chunk(kc, std::integral_constant<int, 0>{});
-    if (kc + 1 < nk) chunk(kc + 1, std::integral_constant<int, 1>{});
-    if (kc + 2 < nk) chunk(kc + 2, std::integral_constant<int, 2>{});
-  }
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): no copy into this workgroup's LDS is still in flight
+  dma_gemm::tile_product<NT, TM, TAIL>(reinterpret_cast<const d2*>(H1), reinterpret_cast<const d2*>(H2), ld,
+                                       reinterpret_cast<const d2*>(a.x), B, B, dim, row0, col0, sc, are[0], aim[0]);
   group_epilogue<NT, TI, TJ, WM, WN, TM, TN>(a, dim, row0, col0, wr, wc, true, are, aim, csum);
 }
 
@@ -564,7 +412,7 @@ template <int TM>
 hipError_t launch_dma_tile(int nterms, const double2* H1, const double2* H2, long long ld, int dim,
                            const MultiArgs& a, hipStream_t s) {
   const int grid = (dim + TM - 1) / TM * ((a.B + 63) / 64);
-  const bool tail = dim % kDmaTK != 0;
+  const bool tail = dim % dma_gemm::kTK != 0;
   if (nterms == 1 && tail) dense_mfma_dma_kernel<1, TM, true><<<grid, TM * 8, 0, s>>>(H1, H2, ld, dim, a);
   else if (nterms == 1) dense_mfma_dma_kernel<1, TM, false><<<grid, TM * 8, 0, s>>>(H1, H2, ld, dim, a);
   else if (tail) dense_mfma_dma_kernel<2, TM, true><<<grid, TM * 8, 0, s>>>(H1, H2, ld, dim, a);
