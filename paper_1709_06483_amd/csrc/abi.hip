@@ -143,7 +143,8 @@ struct magnus_ctx {
   // wave of the GEMV iteration and the FP64-MFMA tile of group iterations
   std::map<std::pair<const void*, int64_t>, int> tuned_dense_rpw, tuned_mfma;
   int dense_rpw_env = 0;   // MAGNUS_DENSE_RPW: 1, 2 or 4 rows per wave of the GEMV iteration (0: tuned or 2)
-  int mfma_tile_env = -1;  // MAGNUS_MFMA_TILE: 0..6 forces an FP64-MFMA tile shape (-1: tuned or 0)
+  int fuse_assembly = 1;   // MAGNUS_ASSEMBLE_FUSED: 0 assembles a dense exponent in a pass of its own
+  int mfma_tile_env = -1;  // MAGNUS_MFMA_TILE: 0..6 forces an FP64-MFMA tile shape (-1: tuned or the size rule)
   int timing = 0;  // 0 off, k >= 1: every k-th launch of each kernel class is bracketed
   int64_t timing_seq[MAGNUS_KERNEL_CSR_LEJA3 + 1] = {};  // launches of each class since enabling
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> records;
@@ -285,6 +286,10 @@ struct ExpOp {
   bool has_interval = false;           // spectral enclosure given (else Weyl from a, b, kappa)
   double lo = 0.0, hi = 0.0;
   const double* m6c = nullptr;         // CSR Method M6: the ten coefficients of the exponent (matrix-free)
+  // dense: the first iteration also assembles `assembled` = fa H1 + fb H2 (+ fk K)
+  bool fuse_assembly = false;
+  double fa = 0.0, fb = 0.0, fk = 0.0;
+  const double2* fK = nullptr;
 };
 
 // Whether the context holds K = i[H1, H2] of this pair of CSR terms.
@@ -344,10 +349,18 @@ int dense_rpw(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
   auto it = ctx->tuned_dense_rpw.find({h->H1.val, h->H1.dim});
   return it == ctx->tuned_dense_rpw.end() ? 2 : it->second;
 }
-int mfma_tile(const magnus_ctx* ctx, const magnus_hamiltonian* h) {
+// Untuned FP64-MFMA tile: the LDS-DMA tiles, 64 x 64 once its grid has a
+// workgroup for every compute unit, else 32 x 64.  Measured (autotuner, us per
+// launch, 32 x 64 / 64 x 64): 512 x 16 states 39.5 / 63.4, 1024 x 128 78.9 /
+// 126.6, 2048 x 256 156.0 / 245.6, 4096 x 128 310.4 / 488.0, 4096 x 256
+// 536.8 / 482.9, 8192 x 64 580.2 / 945.6, 8192 x 256 2,060.6 / 1,908.8; the
+// register-staged tiles were slower at every one of these shapes.
+int mfma_tile(const magnus_ctx* ctx, const magnus_hamiltonian* h, int B) {
   if (ctx->mfma_tile_env >= 0) return ctx->mfma_tile_env;
   auto it = ctx->tuned_mfma.find({h->H1.val, h->H1.dim});
-  return it == ctx->tuned_mfma.end() ? 0 : it->second;
+  if (it != ctx->tuned_mfma.end()) return it->second;
+  const long long blocks = (h->H1.dim + 63) / 64 * ((B + 63) / 64);
+  return blocks >= 256 ? 6 : 5;
 }
 
 hipEvent_t next_event(magnus_ctx* ctx) {
@@ -488,6 +501,17 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
     if (int rc = setup_stop_test(ctx, P, i, grid, &a, s)) return rc;
     const bool fused = a.fused;
     HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_LEJA, s, [&] {
+      if (op.fuse_assembly && i == 1) {
+        const magnus::DenseAssembly D{reinterpret_cast<const double2*>(h->H1.val),
+                                      reinterpret_cast<const double2*>(h->H2.val),
+                                      op.fK,
+                                      h->H1.ld,
+                                      op.fa,
+                                      op.fb,
+                                      op.fk,
+                                      const_cast<double2*>(op.assembled)};
+        return magnus::launch_dense_assemble_iter(D, dim, a, s, rpw);
+      }
       if (op.assembled) return magnus::launch_dense2_iter(op.assembled, nullptr, dim, dim, a, s, rpw);
       return magnus::launch_dense2_iter(reinterpret_cast<const double2*>(h->H1.val),
                                         reinterpret_cast<const double2*>(h->H2.val), dim, h->H1.ld, a, s, rpw);
@@ -576,6 +600,7 @@ int enqueue_exponential(magnus_ctx* ctx, const ExpOp& it, const ExpPlan& P, cons
   const int64_t dim = it.h->H1.dim;
   const int m = P.lp.m, ns = P.lp.s;
   const double2* cur = src;
+  ExpOp op = it;  // a fused assembly happens in the first iteration only
   for (int sub = 0; sub < ns; ++sub) {
     const bool last = (sub == ns - 1);
     double2* Pbuf;
@@ -586,8 +611,9 @@ int enqueue_exponential(magnus_ctx* ctx, const ExpOp& it, const ExpPlan& P, cons
       double2* wout = (i % 2 == 1) ? ctx->vec(kA) : ctx->vec(kB);
       TableRef t{};
       if (tab) t = TableRef{tab->col + (size_t)sub * m + (i - 1), tab->stride, tab->step};
-      int rc = launch_iteration(ctx, it, P, i, win, wout, Pbuf, tol_sub, early, s, tab ? &t : nullptr);
+      int rc = launch_iteration(ctx, op, P, i, win, wout, Pbuf, tol_sub, early, s, tab ? &t : nullptr);
       if (rc) return rc;
+      op.fuse_assembly = false;
     }
     cur = Pbuf;
   }
@@ -624,11 +650,19 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
     if (op.kappa != 0.0 && !dense_comm_ready(ctx, op.h))
       return fail(MAGNUS_EINVAL, "dense commutator exponents need magnus_dense_commutator for this pair of terms");
     if (ctx->assembled_dim < dim) return fail(MAGNUS_ENOMEM, "no assembly buffer (magnus_reserve_dense)");
-    HIP_TRY(magnus::launch_dense_assemble(reinterpret_cast<const double2*>(op.h->H1.val),
-                                          reinterpret_cast<const double2*>(op.h->H2.val), op.h->H1.ld, (int)dim,
-                                          op.a, op.b, op.kappa != 0.0 ? ctx->comm : nullptr, op.kappa,
-                                          ctx->assembled, s));
     it = ExpOp{op.h, 1.0, 0.0, 0.0, ctx->assembled};
+    if (ctx->fuse_assembly) {  // assembled by the first iteration as it goes
+      it.fuse_assembly = true;
+      it.fa = op.a;
+      it.fb = op.b;
+      it.fk = op.kappa;
+      it.fK = op.kappa != 0.0 ? ctx->comm : nullptr;
+    } else {
+      HIP_TRY(magnus::launch_dense_assemble(reinterpret_cast<const double2*>(op.h->H1.val),
+                                            reinterpret_cast<const double2*>(op.h->H2.val), op.h->H1.ld, (int)dim,
+                                            op.a, op.b, op.kappa != 0.0 ? ctx->comm : nullptr, op.kappa,
+                                            ctx->assembled, s));
+    }
   }
   int rc = enqueue_exponential(ctx, it, P, src, dst, tol_sub, o->early_termination, nullptr, s);
   if (rc) return rc;
@@ -941,7 +975,7 @@ int launch_multi(magnus_ctx* ctx, const magnus_hamiltonian* h, const MultiExp& E
                       [&] { return magnus::launch_dense_frechet(D1, D2, dim, h->H1.ld, a, s); }));
       else if (dense)
         HIP_TRY(timed(ctx, MAGNUS_KERNEL_DENSE_MFMA, s,
-                      [&] { return magnus::launch_dense_mfma(E.dense_terms, D1, D2, ldd, dim, a, s, mfma_tile(ctx, h)); }));
+                      [&] { return magnus::launch_dense_mfma(E.dense_terms, D1, D2, ldd, dim, a, s, mfma_tile(ctx, h, B)); }));
       else
         HIP_TRY(timed(ctx, MAGNUS_KERNEL_CSR_MULTI, s, [&] { return magnus::launch_csr2_multi(mode, t1, t2, dim, a, s); }));
       HIP_TRY(magnus::launch_multi_decide(a, grid, s));
@@ -1626,6 +1660,7 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
     const int r = atoi(v);
     c->dense_rpw_env = (r == 1 || r == 2 || r == 4) ? r : 0;
   }
+  if (const char* v = getenv("MAGNUS_ASSEMBLE_FUSED")) c->fuse_assembly = atoi(v);
   if (const char* v = getenv("MAGNUS_MFMA_TILE")) {
     const int t = atoi(v);
     c->mfma_tile_env = (t >= 0 && t < magnus::kMfmaTiles) ? t : -1;

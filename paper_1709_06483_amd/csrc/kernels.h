@@ -159,6 +159,18 @@ int dense_gershgorin_grid(int dim);
 // Dense Leja iteration (mode kLeja only): two terms, or one (an assembled
 // exponent) when H2 is null.
 // rpw: rows per wave (1, 2 or 4).
+// Inputs of the first dense iteration fused with the assembly of its exponent:
+// out = ca H1 + cb H2 (+ ck K), H1 and H2 with row stride ld, K (optional)
+// and out with row stride dim.
+struct DenseAssembly {
+  const double2* H1;
+  const double2* H2;
+  const double2* K;
+  long long ld;
+  double ca, cb, ck;
+  double2* out;
+};
+hipError_t launch_dense_assemble_iter(const DenseAssembly& D, int dim, const IterArgs& a, hipStream_t s, int rpw);
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s, int rpw = 2);
 int dense2_grid(int dim, int nterms, int rpw = 2);

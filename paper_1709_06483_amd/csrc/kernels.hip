@@ -639,6 +639,68 @@ __global__ __launch_bounds__(kThreads) void dense2_iter_kernel(const double2* H1
   block_partials(a, pw, pv);
 }
 
+// The first iteration of an exponential on dense terms fused with the
+// assembly of its exponent: while it streams H1 and H2 (and K) it stores
+// Hs = ca H1 + cb H2 (+ ck K) into the assembly buffer (row stride dim, all
+// stores non-temporal: dim 8192 Cf4 382 steps/s, against 367 with the rows
+// that the next iterations keep in the MALL stored normally and 354 with all
+// stores normal) and multiplies Hs x.  Hs is
+// formed by the same expression as dense_assemble_kernel, and every lane
+// sums the same columns in the same order as the one-term iteration, so the
+// result is bitwise that of assembling first and iterating on the assembled
+// matrix; the separate assembly pass and one full read of the assembled
+// matrix disappear.
+template <int RPW, bool WITH_K>
+__global__ __launch_bounds__(kThreads) void dense_assemble_iter_kernel(DenseAssembly D, int dim, IterArgs a) {
+  __shared__ double fz[kFuseLds];
+  if (iteration_stopped(a, fz)) return;  // a first iteration always runs
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int rbase = (L * (kThreads / 64) + wv) * RPW;
+  const d2* x = reinterpret_cast<const d2*>(a.x1);
+  const d2* A1 = reinterpret_cast<const d2*>(D.H1);
+  const d2* A2 = reinterpret_cast<const d2*>(D.H2);
+  const d2* Kp = reinterpret_cast<const d2*>(D.K);
+  d2 acc[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) acc[r] = d2{0.0, 0.0};
+  int nr = min(RPW, dim - rbase);
+  if (nr < 0) nr = 0;
+  constexpr int UNR = 2;
+  for (int j0 = lane; j0 < dim; j0 += 64 * UNR) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int j = j0 + 64 * u;
+      if (j < dim) {
+        const d2 xj = x[j];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          if (r < nr) {
+            const long long row = rbase + r;
+            d2 h = rmul(D.ca, __builtin_nontemporal_load(A1 + row * D.ld + j)) +
+                   rmul(D.cb, __builtin_nontemporal_load(A2 + row * D.ld + j));
+            if constexpr (WITH_K) h += rmul(D.ck, __builtin_nontemporal_load(Kp + row * dim + j));
+            __builtin_nontemporal_store(h, reinterpret_cast<d2*>(D.out) + row * dim + j);
+            acc[r] += cmul(h, xj);
+          }
+        }
+      }
+    }
+  }
+  double pw = 0.0, pv = 0.0;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    d2 s1 = acc[r];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1.x += __shfl_xor(s1.x, off, 64);
+      s1.y += __shfl_xor(s1.y, off, 64);
+    }
+    if (lane == r && r < nr) leja_row(a, rbase + r, rmul(a.a1, s1), pw, pv);
+  }
+  block_partials(a, pw, pv);
+}
+
 // ---------------------------------------------------------------------------
 // The Method M6 iteration on CSR terms (the exponent's nested commutators
 // applied to vectors as commutators of assembled CSR matrices), in two
@@ -902,6 +964,23 @@ int dense2_grid(int dim, int nterms, int rpw) {
 // MALL budget kept for matrix rows: its 256 MiB less a margin and the vectors
 // an iteration touches (x, w and p read, w and p written).
 constexpr long long kDenseMallKeepBytes = 240LL << 20;
+
+hipError_t launch_dense_assemble_iter(const DenseAssembly& D, int dim, const IterArgs& a, hipStream_t s, int rpw) {
+  const int g = dense2_grid(dim, 1, rpw);
+#define MAGNUS_DENSE_ASM_CASE(R)                                                        \
+  case R:                                                                               \
+    if (D.K) dense_assemble_iter_kernel<R, true><<<g, kThreads, 0, s>>>(D, dim, a);      \
+    else dense_assemble_iter_kernel<R, false><<<g, kThreads, 0, s>>>(D, dim, a);         \
+    break;
+  switch (rpw) {
+    MAGNUS_DENSE_ASM_CASE(1)
+    MAGNUS_DENSE_ASM_CASE(2)
+    MAGNUS_DENSE_ASM_CASE(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef MAGNUS_DENSE_ASM_CASE
+  return hipGetLastError();
+}
 
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s, int rpw) {

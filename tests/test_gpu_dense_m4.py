@@ -110,3 +110,44 @@ def test_dense_single_state_assembled_cf4():
     ref = mg.propagate("CF4", mg.two_term(H0, V, f), tau, nsteps, psi0, expm="eig")
     assert rel(host(psi), ref) <= BUDGET
     c.close()
+
+
+@pytest.mark.parametrize("method,N,pad,rpw", [("CF4", 300, 0, "2"), ("CF4", 257, 5, "1"), ("M4", 130, 7, "4"),
+                                              ("M4", 200, 0, "2")])
+def test_dense_fused_assembly_is_bitwise_the_separate_pass(method, N, pad, rpw, monkeypatch):
+    """The first iteration of a dense exponent assembles it as it goes (H1 and H2 with
+    row stride N + pad, K and the assembled matrix with stride N; 1, 2 or 4 rows per
+    wave): the states equal, bit for bit, those of assembling in a pass of its own and
+    then iterating, and both match the oracle."""
+    monkeypatch.setenv("MAGNUS_DENSE_RPW", rpw)
+    H0 = inputs.powerlaw_hermitian(N, 1.5, seed=90)
+    V = inputs.powerlaw_hermitian(N, 1.5, seed=91)
+    psi0 = inputs.random_states(N, seed=92)
+    tau, nsteps = 0.02, 6
+    f = inputs.sin_field(1.0, 2.0)
+    fn = nodes(method, f, tau, nsteps)
+    out = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("MAGNUS_ASSEMBLE_FUSED", fused)
+        c = B.Context(max_dim=N, max_batch=1)
+        c.reserve_dense(N)
+        if pad:
+            P0 = torch.zeros((N, N + pad), dtype=torch.complex128, device="cuda")
+            P1 = torch.zeros((N, N + pad), dtype=torch.complex128, device="cuda")
+            P0[:, :N] = dev(H0)
+            P1[:, :N] = dev(V)
+            ham = B.DeviceHamiltonian.from_dense(P0[:, :N], P1[:, :N])
+        else:
+            ham = B.DeviceHamiltonian.from_dense(H0, V)
+        ham = B.magnus_spectral_bounds(c, ham)
+        if method == "M4":
+            B.magnus_dense_commutator(c, ham)
+        psi = dev(psi0)
+        _, st = B.propagate(c, ham, B.METHODS[method], tau, fn, psi, opts=B.leja_opts(BUDGET, tol_mode=1),
+                            stats=True)
+        assert st["max_degree_used"] >= 4
+        out[fused] = host(psi)
+        c.close()
+    assert np.array_equal(out["1"], out["0"])
+    ref = mg.propagate(method, mg.two_term(H0, V, f), tau, nsteps, psi0, expm="eig")
+    assert rel(out["1"], ref) <= BUDGET
