@@ -113,6 +113,37 @@ def test_batched_dense_4096_x256_sampled_columns():
     ctx.close()
 
 
+@pytest.mark.parametrize("tile", ["5", "6"])
+def test_batched_dense_4096_x256_per_state_fields_sampled_columns(tile, monkeypatch):
+    """The c3 batch with a field amplitude per state, so each group iteration is the
+    two-term FP64-MFMA GEMM (per-state coefficients folded into the W operand), on
+    both LDS-DMA tiles: one Cf4 step, three sampled columns against the oracle."""
+    monkeypatch.setenv("MAGNUS_MFMA_TILE", tile)
+    cfg = inputs.CONFIGS["batched_dense_4096"]
+    N, Bn, tau = cfg["N"], cfg["batch"], cfg["tau"]
+    H0 = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["H0"])
+    V = inputs.powerlaw_hermitian(N, cfg["alpha"], cfg["seeds"]["V"])
+    fields = [inputs.sin_field(cfg["omega"], 1.0 + k / Bn) for k in range(Bn)]
+    psi0 = inputs.random_states(N, seed=cfg["seeds"]["psi"], batch=Bn)
+    tol_e = cfg["budget_tol"] / (2 * cfg["nsteps"])
+    ctx = B.Context(max_dim=N, max_batch=Bn)
+    ham = B.magnus_spectral_bounds(ctx, B.DeviceHamiltonian.from_dense(H0, V))
+    fn = np.stack([nodes("CF4", fk, 0.0, tau, 1) for fk in fields])
+    psi = torch.from_numpy(psi0).cuda()
+    ctx.timing(True)
+    B.propagate(ctx, ham, B.CF4, tau, fn, psi, opts=B.leja_opts(tol_e))
+    _, gemms = ctx.timing_read(B.KERNEL_DENSE_MFMA)
+    ctx.timing(False)
+    assert gemms > 0
+    got = psi.cpu().numpy()
+    for c in (0, 100, 255):
+        ref = mg.propagate("CF4", mg.two_term(H0, V, fields[c]), tau, 1, psi0[c], expm="taylor")
+        e = rel(got[c], ref)
+        say(f"dense 4096 x 256 per-state fields, tile {tile}, column {c}, 1 Cf4 step: {e:.3e}")
+        assert e <= 50 * tol_e * 2
+    ctx.close()
+
+
 def test_ragged_chains_12_to_18_x16_sampled_instances():
     cfg = inputs.CONFIGS["ragged_chains"]
     tau, per, nsteps = cfg["tau"], cfg["per_size"], 3
