@@ -143,6 +143,7 @@ struct magnus_ctx {
   // wave of the GEMV iteration and the FP64-MFMA tile of group iterations
   std::map<std::pair<const void*, int64_t>, int> tuned_dense_rpw, tuned_mfma;
   int dense_rpw_env = 0;   // MAGNUS_DENSE_RPW: 1, 2 or 4 rows per wave of the GEMV iteration (0: tuned or 2)
+  int persist_cache = 1;   // MAGNUS_PERSIST_CACHE: 0 keeps the small-state kernel's term 1 out of LDS
   int fuse_assembly = 1;   // MAGNUS_ASSEMBLE_FUSED: 0 assembles a dense exponent in a pass of its own
   int mfma_tile_env = -1;  // MAGNUS_MFMA_TILE: 0..6 forces an FP64-MFMA tile shape (-1: tuned or the size rule)
   int timing = 0;  // 0 off, k >= 1: every k-th launch of each kernel class is bracketed
@@ -1332,6 +1333,9 @@ int persist_segment(magnus_ctx* ctx, const std::vector<const magnus_hamiltonian*
   a.nexp = nexp;
   a.slots = ctx->slots;
   a.early = o->early_termination;
+  // term 1 in LDS: one workgroup per CU then, so only while the states fit the chip
+  a.cache1 = ctx->persist_cache && maxdim <= 1024 && nst <= 256;
+  for (const magnus_hamiltonian* h : hs) a.cache1 = a.cache1 && h->H1.nnz <= magnus::kPersistCache;
   HIP_TRY(timed(ctx, MAGNUS_KERNEL_PERSIST, s, [&] { return magnus::launch_persist_propagate(a, nst, (int)maxdim, s); }));
   return MAGNUS_OK;
 }
@@ -1661,6 +1665,7 @@ int magnus_create(magnus_ctx** out, int64_t max_dim, int32_t max_batch, int32_t 
     c->dense_rpw_env = (r == 1 || r == 2 || r == 4) ? r : 0;
   }
   if (const char* v = getenv("MAGNUS_ASSEMBLE_FUSED")) c->fuse_assembly = atoi(v);
+  if (const char* v = getenv("MAGNUS_PERSIST_CACHE")) c->persist_cache = atoi(v);
   if (const char* v = getenv("MAGNUS_MFMA_TILE")) {
     const int t = atoi(v);
     c->mfma_tile_env = (t >= 0 && t < magnus::kMfmaTiles) ? t : -1;

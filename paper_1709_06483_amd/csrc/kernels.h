@@ -156,9 +156,6 @@ hipError_t launch_dense_gershgorin(const double2* H, int dim, long long ld, doub
                                    hipStream_t s);
 int dense_gershgorin_grid(int dim);
 
-// Dense Leja iteration (mode kLeja only): two terms, or one (an assembled
-// exponent) when H2 is null.
-// rpw: rows per wave (1, 2 or 4).
 // Inputs of the first dense iteration fused with the assembly of its exponent:
 // out = ca H1 + cb H2 (+ ck K), H1 and H2 with row stride ld, K (optional)
 // and out with row stride dim.
@@ -171,6 +168,9 @@ struct DenseAssembly {
   double2* out;
 };
 hipError_t launch_dense_assemble_iter(const DenseAssembly& D, int dim, const IterArgs& a, hipStream_t s, int rpw);
+// Dense Leja iteration (mode kLeja only): two terms, or one (an assembled
+// exponent) when H2 is null.
+// rpw: rows per wave (1, 2 or 4).
 hipError_t launch_dense2_iter(const double2* H1, const double2* H2, int dim, long long ld,
                               const IterArgs& a, hipStream_t s, int rpw = 2);
 int dense2_grid(int dim, int nterms, int rpw = 2);
@@ -347,10 +347,13 @@ struct PersistArgs {
   int nexp;                // exponentials per state (even: Cf4 pairs)
   Slot* slots;             // one per state
   int early;
+  int cache1;              // every problem's term 1 fits kPersistCache entries (dim <= 1024)
 };
 
 // Largest dimension of the one-workgroup-per-state kernel (two LDS vectors).
 constexpr int kPersistMaxDim = 4096;
+// Entries of term 1 the dim <= 1024 kernel keeps in LDS beside its two vectors.
+constexpr int kPersistCache = 6400;
 hipError_t launch_persist_propagate(const PersistArgs& a, int nstates, int max_dim, hipStream_t s);
 
 // Small helpers.

@@ -527,6 +527,38 @@ def test_small_state_propagation_paths_agree(persist, monkeypatch):
     c.close()
 
 
+def test_small_state_kernel_term1_in_lds_is_bitwise_the_uncached(monkeypatch):
+    """The one-workgroup kernel keeps term 1 of problems of at most 1024 rows in LDS
+    when it fits (chains of 8 and 10 spins in one launch; a random pair of 1000 rows
+    whose term 1 holds too many entries, which stays uncached): states equal bit for
+    bit those with the cache switched off, and match the oracle."""
+    monkeypatch.setenv("MAGNUS_PERSIST", "1")
+    tau, nsteps = 0.01, 8
+    terms = [chain(8), chain(10), (_ragged_hermitian(1000, 41), _ragged_hermitian(1000, 42))]
+    assert terms[2][0].to_scipy().nnz > 6400 >= terms[1][0].to_scipy().nnz
+    out = {}
+    for cache in ("1", "0"):
+        monkeypatch.setenv("MAGNUS_PERSIST_CACHE", cache)
+        c = B.Context(max_dim=1024, max_batch=2)
+        for idx, (H1, H2) in enumerate(terms):
+            N = H1.to_scipy().shape[0]
+            ham = B.magnus_spectral_bounds(c, B.DeviceHamiltonian.from_csr(H1, H2))
+            psi0 = inputs.random_states(N, seed=500 + idx, batch=2)
+            fields = [inputs.cos_field(2.0, a) for a in (1.0, -0.7)]
+            fn = np.stack([_field_nodes("CF4", f, 0.0, tau, nsteps) for f in fields])
+            psi = dev(psi0)
+            B.propagate(c, ham, B.CF4, tau, fn, psi, opts=B.leja_opts(BUDGET, tol_mode=1))
+            out[cache, idx] = host(psi)
+            if cache == "1":
+                for k in range(2):
+                    P = mg.two_term(H1.to_scipy(), H2.to_scipy(), fields[k])
+                    ref = mg.propagate("CF4", P, tau, nsteps, psi0[k], expm="taylor")
+                    assert rel(out[cache, idx][k], ref) <= BUDGET, (idx, k)
+        c.close()
+    for idx in range(len(terms)):
+        assert np.array_equal(out["1", idx], out["0", idx]), idx
+
+
 @pytest.mark.parametrize("persist", ["1", "0"])
 def test_ragged_batch_matches_oracle(persist, monkeypatch):
     """Chains of 8, 10, 12 and 15 spins with several states each, one call: the
