@@ -287,10 +287,12 @@ struct ExpOp {
   bool has_interval = false;           // spectral enclosure given (else Weyl from a, b, kappa)
   double lo = 0.0, hi = 0.0;
   const double* m6c = nullptr;         // CSR Method M6: the ten coefficients of the exponent (matrix-free)
-  // dense: the first iteration also assembles `assembled` = fa H1 + fb H2 (+ fk K)
+  // dense: the first iteration also writes the assembled exponent
+  // fuse_out = fa H1 + fb H2 (+ fk K), the matrix `assembled` points to
   bool fuse_assembly = false;
   double fa = 0.0, fb = 0.0, fk = 0.0;
   const double2* fK = nullptr;
+  double2* fuse_out = nullptr;
 };
 
 // Whether the context holds K = i[H1, H2] of this pair of CSR terms.
@@ -510,7 +512,7 @@ int launch_iteration(magnus_ctx* ctx, const ExpOp& op, const ExpPlan& P, int i, 
                                       op.fa,
                                       op.fb,
                                       op.fk,
-                                      const_cast<double2*>(op.assembled)};
+                                      op.fuse_out};
         return magnus::launch_dense_assemble_iter(D, dim, a, s, rpw);
       }
       if (op.assembled) return magnus::launch_dense2_iter(op.assembled, nullptr, dim, dim, a, s, rpw);
@@ -658,6 +660,7 @@ int run_exponential(magnus_ctx* ctx, const ExpOp& op, double tau, const double2*
       it.fb = op.b;
       it.fk = op.kappa;
       it.fK = op.kappa != 0.0 ? ctx->comm : nullptr;
+      it.fuse_out = ctx->assembled;
     } else {
       HIP_TRY(magnus::launch_dense_assemble(reinterpret_cast<const double2*>(op.h->H1.val),
                                             reinterpret_cast<const double2*>(op.h->H2.val), op.h->H1.ld, (int)dim,
