@@ -711,6 +711,8 @@ __global__ __launch_bounds__(kThreads) void dense_assemble_iter_kernel(DenseAsse
 //   stage B: y = y0 + sum_k M_k u_k, then the Leja update and norm partials.
 // Grouping the products by matrix reads P1 and P2 twice per iteration where
 // applying each commutator product separately reads them three and four times.
+// A lane loads its row's bounds in all five matrices before the first product,
+// so those loads are in flight together (n = 16: 2,263 against 2,197 steps/s).
 // ---------------------------------------------------------------------------
 constexpr int kM6Lanes = 8;  // lanes per row
 
@@ -723,12 +725,18 @@ __global__ __launch_bounds__(kThreads) void m6_stage_a_kernel(M6Terms T, const d
   const int r = (int)(t / kM6Lanes), q = (int)(t % kM6Lanes);
   const d2* wv = reinterpret_cast<const d2*>(w);
   d2 sk[kM6Terms];
+  int rs[kM6Terms], re[kM6Terms];
+#pragma unroll
+  for (int k = 0; k < kM6Terms; ++k) {
+    rs[k] = r < dim ? T.m[k].rp[r] : 0;
+    re[k] = r < dim ? T.m[k].rp[r + 1] : 0;
+  }
 #pragma unroll
   for (int k = 0; k < kM6Terms; ++k) {
     d2 acc = {0.0, 0.0};
-    if (r < dim) {
+    {
       const d2* av = reinterpret_cast<const d2*>(T.m[k].val);
-      for (int e = T.m[k].rp[r] + q; e < T.m[k].rp[r + 1]; e += kM6Lanes) acc += cmul(av[e], wv[T.m[k].ci[e]]);
+      for (int e = rs[k] + q; e < re[k]; e += kM6Lanes) acc += cmul(av[e], wv[T.m[k].ci[e]]);
     }
 #pragma unroll
     for (int off = kM6Lanes / 2; off > 0; off >>= 1) {
@@ -764,11 +772,17 @@ __global__ __launch_bounds__(kThreads) void m6_stage_b_kernel(M6Terms T, M6Vecs 
   const int r = r0 < dim ? dim - 1 - r0 : r0;
   d2 acc = {0.0, 0.0};
   if (r < dim) {
+    int rs[kM6Terms], re[kM6Terms];
+#pragma unroll
+    for (int k = 0; k < kM6Terms; ++k) {
+      rs[k] = T.m[k].rp[r];
+      re[k] = T.m[k].rp[r + 1];
+    }
 #pragma unroll
     for (int k = 0; k < kM6Terms; ++k) {
       const d2* av = reinterpret_cast<const d2*>(T.m[k].val);
       const d2* uv = reinterpret_cast<const d2*>(V.u[k]);
-      for (int e = T.m[k].rp[r] + q; e < T.m[k].rp[r + 1]; e += kM6Lanes) acc += cmul(av[e], uv[T.m[k].ci[e]]);
+      for (int e = rs[k] + q; e < re[k]; e += kM6Lanes) acc += cmul(av[e], uv[T.m[k].ci[e]]);
     }
   }
 #pragma unroll
