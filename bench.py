@@ -680,7 +680,7 @@ def compact_extras(args):
     ex = {}
     t0 = time.perf_counter()
     a = copy.copy(args)
-    a.steps, a.warmup = 4, 1
+    a.steps, a.warmup = 8, 2
     d = other_workload("batched_dense_4096", a, emit=False)
     ex["batched_dense_4096"] = {k: d[k] for k in ("steps", "state_steps_per_s", "plain_state_steps_per_s",
                                                   "batched_vs_plain", "mfma_tflops", "mfma_util_vs_78.6TF",
